@@ -1,0 +1,241 @@
+/*
+ * qsim.h -- C ABI of the MI355X state-vector simulator.
+ *
+ * The library applies long sequences of 1- and 2-qubit gates (and k <= 5
+ * qubit gates) to a 2^n-amplitude complex state held in device memory, with
+ * gate fusion, simulated mid-circuit measurement and measurement assertion,
+ * and FP64 observables.  Section numbers below are those of the paper
+ * "Deep Quantum Circuit Simulations of Low-energy Nuclear States"
+ * (arXiv:2310.17739).
+ *
+ * General rules
+ *  - Every call returns an int status: QSIM_OK (0) or a negative QSIM_E_*.
+ *    No C++ exception crosses this boundary.  On error the state is left as
+ *    it was before the call (batched and served runs report per-state
+ *    status instead).
+ *  - A state handle is not thread-safe; distinct handles may be used from
+ *    distinct threads.
+ *  - Host arrays passed in (gates, matrices, parameters, terms) are owned by
+ *    the caller and are copied before the call returns.
+ *  - Device buffers passed in (the state) are owned by the caller (in the
+ *    Python binding: a torch tensor) and must outlive the handle.
+ *  - qsim_apply is asynchronous on the handle's stream.  Calls that return
+ *    host values (measure, reset, expval, probs, norm, get_state) synchronise
+ *    that stream.
+ *
+ * Conventions
+ *  - Amplitude index i = sum_q b_q 2^q: qubit q is bit q (Section 3.2,
+ *    Eq. (1q-op) pairs a[s] with a[s + 2^q]).
+ *  - State storage is interleaved (re, im): complex64 (2 x float) or
+ *    complex128 (2 x double), contiguous, 2^n elements.
+ *  - A gate record on qubits (q[0], ..., q[k-1]) defines its matrix on the
+ *    local index r = sum_j bit(q[j]) 2^j.  Controlled gates list their
+ *    controls first and their target last.  R_P(theta) = exp(-i theta P/2).
+ */
+#ifndef QSIM_H
+#define QSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qsim_state *qsim_h;
+
+/* state storage precision */
+enum { QSIM_C64 = 1, QSIM_C128 = 2 };
+
+/* status codes */
+enum {
+    QSIM_OK = 0,
+    QSIM_E_ARG = -1,          /* bad argument (non-finite angle, u outside [0,1), mask >= 2^n ...) */
+    QSIM_E_QUBIT = -2,        /* qubit >= n, or repeated inside one gate */
+    QSIM_E_NOMEM = -3,        /* device or host allocation failed */
+    QSIM_E_ZERO_PROB = -4,    /* assertion of an outcome whose probability is exactly 0 */
+    QSIM_E_NOT_DEFINITE = -5, /* reset of a qubit that is in superposition */
+    QSIM_E_HIP = -6,          /* HIP runtime error */
+    QSIM_E_CAPACITY = -7,     /* state or request larger than the buffer / pool */
+    QSIM_E_UNSUPPORTED = -8   /* gate kind or option not supported */
+};
+
+/* Gate kinds: the OpenQASM 2.0 table of Section 4.1 (Table 3), a general
+ * matrix record, and the non-unitary records of Listing 1 (Section 4.3). */
+enum {
+    QSIM_G_ID = 0, QSIM_G_H = 1, QSIM_G_X = 2, QSIM_G_Y = 3, QSIM_G_Z = 4,
+    QSIM_G_S = 5, QSIM_G_SDG = 6, QSIM_G_T = 7, QSIM_G_TDG = 8, QSIM_G_SX = 9,
+    QSIM_G_RX = 10, QSIM_G_RY = 11, QSIM_G_RZ = 12, QSIM_G_U1 = 13,
+    QSIM_G_U2 = 14, QSIM_G_U3 = 15,
+    QSIM_G_CX = 20, QSIM_G_CY = 21, QSIM_G_CZ = 22, QSIM_G_CH = 23,
+    QSIM_G_SWAP = 24, QSIM_G_CRX = 25, QSIM_G_CRY = 26, QSIM_G_CRZ = 27,
+    QSIM_G_CU1 = 28, QSIM_G_CU3 = 29, QSIM_G_RXX = 30, QSIM_G_RZZ = 31,
+    QSIM_G_CCX = 40, QSIM_G_CSWAP = 41, QSIM_G_C3X = 44, QSIM_G_C3XSQRTX = 45,
+    QSIM_G_C4X = 46,
+    QSIM_G_MAT = 50,      /* 2^nq x 2^nq complex128 matrix from the pool */
+    QSIM_G_BARRIER = 60,  /* fusion fence */
+    QSIM_G_MEASURE = 61,  /* Born-rule measurement (batched programs only) */
+    QSIM_G_RESET = 62,    /* reset of a definite qubit (batched programs only) */
+    QSIM_G_ASSERT0 = 63   /* measurement assertion of outcome 0 (batched programs only) */
+};
+
+/* One gate record (56 bytes). */
+typedef struct qsim_gate {
+    uint16_t kind;     /* QSIM_G_* */
+    uint16_t nq;       /* qubits named in q[] (1..5) */
+    int32_t q[5];      /* qubits: controls first, target last */
+    int32_t slot;      /* -1: theta[] literal.  >= 0 on a rotation: theta[0]
+                          is read from the per-circuit parameter vector at
+                          this index.  On MEASURE / ASSERT0: the measurement
+                          slot (index of its uniform draw and its outputs). */
+    uint32_t mat_off;  /* MAT: offset, in complex entries, into the pool */
+    double theta[3];   /* angles in radians */
+} qsim_gate;
+
+/* One Pauli-sum term: letter on qubit j is I (x=0,z=0), X (1,0), Z (0,1)
+ * or Y (1,1) for the bits j of xmask and zmask. */
+typedef struct qsim_pauli {
+    double coeff;
+    uint64_t xmask;
+    uint64_t zmask;
+} qsim_pauli;
+
+/* Fusion and pass-planning options.  NULL selects the tuned defaults. */
+typedef struct qsim_fuse_opts {
+    int32_t level;       /* 0 none; 1 F1 (1q+1q); 2 F1+F3 (2q absorbs 1q);
+                            3 = 2 + F2 on identically ordered pairs;
+                            4 = 2 + SWAP normalisation + F2 (the paper's
+                            strategy, Section 4.2, Fig. 4);
+                            5 = 4 + cost-driven fusion into k <= max_width
+                            qubit operators (default) */
+    int32_t max_width;   /* 2..5 (complex128 is limited to 4); 0 = default */
+    int32_t tile_qubits; /* qubits per LDS tile; 0 = default for n and dtype */
+    int32_t flags;       /* QSIM_F_* */
+} qsim_fuse_opts;
+
+enum {
+    QSIM_F_ONE_OP_PER_PASS = 1,  /* every fused operator is its own full-state sweep */
+    QSIM_F_NO_SPARSE = 2         /* treat fused operators as dense (no zero skipping) */
+};
+
+/* Counters of the last qsim_apply (host-side compile and device plan). */
+typedef struct qsim_apply_stats {
+    int64_t input_gates;      /* gate records, barriers excluded */
+    int64_t ops_after[6];     /* operators after fusion level 0..5 (those computed) */
+    int64_t fused_ops;        /* operators executed */
+    int64_t passes;           /* full-state read+write passes enqueued */
+    int64_t terms;            /* sum over operators of their nonzero XOR diagonals */
+    int64_t bytes_moved;      /* algorithmic HBM bytes of the passes: passes * 2 * 2^n * elem */
+    double compile_seconds;   /* host time spent lowering, fusing, planning, packing */
+    int32_t tile_qubits;      /* tile size used */
+    int32_t max_width;        /* fusion width used */
+} qsim_apply_stats;
+
+/* ------------------------------------------------------------------ core */
+
+/* Bind a state to a caller-owned device buffer of at least 2^n elements
+ * (8 bytes each for QSIM_C64, 16 for QSIM_C128) and set it to |0...0>.
+ * `hip_stream` is a hipStream_t (NULL = default stream).  1 <= n <= 40.
+ * Errors: QSIM_E_ARG, QSIM_E_CAPACITY (buffer too small), QSIM_E_NOMEM. */
+int qsim_create(int n, int dtype, void *dev_buf, size_t buf_bytes,
+                void *hip_stream, qsim_h *out);
+int qsim_destroy(qsim_h h);
+int qsim_set_stream(qsim_h h, void *hip_stream);
+int qsim_init_zero(qsim_h h);   /* |0...0>, asynchronous */
+
+/* Apply U_{m-1} ... U_0 (Section 3.2) given as gate records.  MAT records
+ * read their matrices from `mats` (interleaved complex128); records with
+ * slot >= 0 read theta[0] from `params`.  BARRIER records fence fusion.
+ * MEASURE / RESET / ASSERT0 records are rejected (QSIM_E_UNSUPPORTED): use
+ * the calls below, or qsim_batch_* for programs with device-side decisions.
+ * Errors: QSIM_E_QUBIT, QSIM_E_ARG, QSIM_E_UNSUPPORTED, QSIM_E_NOMEM,
+ * QSIM_E_HIP.  Asynchronous. */
+int qsim_apply(qsim_h h, const qsim_gate *g, size_t ng, const double *mats,
+               const double *params, const qsim_fuse_opts *opt);
+int qsim_last_stats(qsim_h h, qsim_apply_stats *out);
+
+/* Born-rule measurement of qubit q (Section 4.3): P0, P1 are reduced in
+ * FP64, p0 = P0/(P0+P1), outcome = (u < p0) ? 0 : 1, the state is projected
+ * and renormalised to unit norm (scale computed in FP64).  u in [0,1).
+ * Writes the outcome and its probability.  Synchronous. */
+int qsim_measure(qsim_h h, int q, double u, int *outcome, double *p_outcome);
+
+/* Measurement assertion (Section 4.3): if P(q = 0) > 0 the outcome is taken
+ * as 0, the state is projected and renormalised and P(q = 0) is written;
+ * otherwise QSIM_E_ZERO_PROB and the state is untouched. */
+int qsim_measure_assert(qsim_h h, int q, double *p_zero);
+
+/* Reset (Listing 1): identity if qubit q is |0>, X if it is |1>;
+ * QSIM_E_NOT_DEFINITE (state untouched) if it is in superposition. */
+int qsim_reset(qsim_h h, int q);
+
+/* <psi|H|psi> / <psi|psi> for H = sum_k coeff_k P_k, accumulated in FP64
+ * with a fixed reduction order.  Masks must be < 2^n. */
+int qsim_expval(qsim_h h, const qsim_pauli *t, size_t nt, double *out);
+
+/* Marginal probabilities of qubits qs[0..nqs-1] (nqs <= 12), normalised by
+ * <psi|psi>: out[j], j = sum_i bit(qs[i]) 2^i, 2^nqs doubles. */
+int qsim_probs(qsim_h h, const int *qs, int nqs, double *out);
+
+/* <psi|psi> in FP64. */
+int qsim_norm(qsim_h h, double *out);
+
+/* Copy the state to / from host memory (2^n elements of the state dtype). */
+int qsim_get_state(qsim_h h, void *host_dst);
+int qsim_set_state(qsim_h h, const void *host_src);
+
+/* ------------------------------------------------- compiled programs */
+
+/* A circuit compiled once (lowering, fusion, pass plan) with its operator
+ * tables resident in device memory, replayable on any state of the same
+ * width and dtype.  qsim_apply is compile + run + free. */
+typedef struct qsim_program *qsim_prog;
+
+/* Compile and upload (synchronous).  Same inputs and errors as qsim_apply. */
+int qsim_compile(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
+                 const double *params, const qsim_fuse_opts *opt, qsim_prog *out);
+/* Enqueue the program's passes on the handle's stream (asynchronous).
+ * QSIM_E_ARG if the width or dtype differ from the handle's. */
+int qsim_run(qsim_h h, qsim_prog p);
+/* Capture the program's launches on `h` into a HIP graph (enable = 1) so that
+ * qsim_run replays the graph; enable = 0 drops the graph.  The graph is tied
+ * to h's state buffer. */
+int qsim_program_graph(qsim_prog p, qsim_h h, int enable);
+/* Enqueue the passes with a HIP event pair around every launch; after the
+ * stream is synchronised, qsim_program_kernel_ms returns the summed
+ * kernel time (ms) of the last timed run and the number of launches. */
+int qsim_run_timed(qsim_h h, qsim_prog p);
+int qsim_program_kernel_ms(qsim_prog p, double *ms, int64_t *launches);
+int qsim_program_stats(qsim_prog p, qsim_apply_stats *out);
+int qsim_program_destroy(qsim_prog p);
+
+/* ------------------------------------------------------- host-only tools */
+
+/* Run lowering and fusion only (no device): writes the fused operators as
+ * (k, qubits, matrix) so that a checker can apply them.  For each operator
+ * i: out_k[i], out_qubits[5*i .. 5*i+k-1] (ascending), and its 4^k complex
+ * entries (row-major, local index bit j = j-th smallest qubit) appended to
+ * out_mats (interleaved doubles).  Capacities in operators / doubles;
+ * QSIM_E_CAPACITY if too small.  `counts` (6 entries, may be NULL) receives
+ * the operator count after each fusion level. */
+int qsim_debug_fuse(int n, const qsim_gate *g, size_t ng, const double *mats,
+                    const double *params, const qsim_fuse_opts *opt,
+                    int32_t *out_k, int32_t *out_qubits, double *out_mats,
+                    size_t cap_ops, size_t cap_doubles, size_t *n_ops,
+                    int64_t *counts);
+
+/* Host-only: number of full-state passes the planner makes for the fused
+ * circuit (same inputs as qsim_debug_fuse), for n qubits and dtype. */
+int qsim_debug_plan(int n, int dtype, const qsim_gate *g, size_t ng,
+                    const double *mats, const double *params,
+                    const qsim_fuse_opts *opt, qsim_apply_stats *out);
+
+const char *qsim_strerror(int status);
+/* Text of the last failed HIP call on this thread (empty if none). */
+const char *qsim_last_error(void);
+int qsim_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QSIM_H */

@@ -1,0 +1,770 @@
+// C ABI of the simulator (include/qsim.h): state handles, the compile ->
+// upload -> launch path of qsim_apply, and the measurement / observable
+// calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "host.h"
+#include "launch.h"
+#include "runtime.h"
+
+using namespace qs;
+
+namespace {
+thread_local char g_last_error[256] = "";
+}
+
+namespace qk {
+int note_hip(hipError_t e, const char *where) {
+    if (e == hipSuccess) return QSIM_OK;
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", where, hipGetErrorString(e), int(e));
+    return QSIM_E_HIP;
+}
+}  // namespace qk
+
+namespace qs {
+
+size_t elem_bytes(int dtype) { return dtype == QSIM_C64 ? 8 : 16; }
+
+int env_int(const char *name, int dflt) {
+    const char *v = std::getenv(name);
+    return (v && *v) ? std::atoi(v) : dflt;
+}
+
+int resident_max(int dtype) {
+    // the whole state in one workgroup's LDS (128 KiB of the 160 KiB)
+    return dtype == QSIM_C64 ? 14 : 13;
+}
+
+void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc, PlanConfig *pc) {
+    fc->level = 5;
+    fc->max_width = 4;
+    fc->sparse = true;
+    fc->max_params = 0;
+    pc->one_op_per_pass = false;
+    pc->tile_qubits = env_int("QSIM_TILE_QUBITS", dtype == QSIM_C64 ? 13 : 12);
+    pc->low_qubits = env_int("QSIM_LOW_QUBITS", dtype == QSIM_C64 ? 4 : 3);
+    pc->window = env_int("QSIM_PLAN_WINDOW", 1024);
+    pc->max_tile_k = dtype == QSIM_C64 ? 5 : 4;
+    if (opt) {
+        if (opt->level >= 0 && opt->level <= 5) fc->level = opt->level;
+        if (opt->max_width > 0) fc->max_width = opt->max_width;
+        if (opt->tile_qubits > 0) pc->tile_qubits = opt->tile_qubits;
+        pc->one_op_per_pass = (opt->flags & QSIM_F_ONE_OP_PER_PASS) != 0;
+        fc->sparse = (opt->flags & QSIM_F_NO_SPARSE) == 0;
+    }
+    if (dtype == QSIM_C128) fc->max_width = std::min(fc->max_width, 4);
+    fc->max_width = std::max(1, std::min(fc->max_width, kMaxK));
+    fc->lds_cost = pc->one_op_per_pass ? 64.0 : 3.0;
+    pc->tile_qubits = std::max(6, std::min(pc->tile_qubits, resident_max(dtype)));
+    if (n <= resident_max(dtype)) pc->tile_qubits = n;
+    if (pc->tile_qubits > n) pc->tile_qubits = n;
+    pc->low_qubits = std::max(0, std::min(pc->low_qubits, pc->tile_qubits - 1));
+    // LDS behind the tile for the pass's records and coefficients: keep two
+    // workgroups per CU for tiles up to 64 KiB, else use what is left
+    const size_t tile_bytes = (size_t(1) << pc->tile_qubits) * elem_bytes(dtype);
+    const size_t lds = qk::max_lds_bytes() - 1024;
+    pc->meta_budget = tile_bytes <= 64 * 1024 ? std::min<size_t>(16 * 1024, lds - tile_bytes)
+                                              : lds - tile_bytes;
+    pc->meta_budget = std::min<size_t>(pc->meta_budget, size_t(env_int("QSIM_META_BUDGET", 1 << 30)));
+}
+
+// Check, before anything is launched, that every device record stays inside
+// the buffers and tiles the kernels will index: tile qubits partition the n
+// qubits, operator positions are ascending and inside the tile (or the
+// state), and coefficient ranges lie inside the coefficient table.
+int validate_plan(int n, int dtype, const Compiled &c) {
+    const PackedPlan &p = c.plan;
+    if (p.pass_begin.size() != c.passes.size() + 1 || p.coef_begin.size() != c.passes.size() + 1)
+        return QSIM_E_ARG;
+    const uint64_t all = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
+    for (size_t i = 0; i < c.passes.size(); i++) {
+        const PassInfo &pi = c.passes[i];
+        int width = n;
+        if (!pi.strided) {
+            const qk::TileArgs &ta = pi.ta;
+            if (ta.n != n || ta.t < 1 || ta.t > n || ta.t > resident_max(dtype) || ta.c < 0 ||
+                ta.c > ta.t || ta.nhi != ta.t - ta.c || n - ta.t > 31)
+                return QSIM_E_ARG;
+            uint64_t m = (uint64_t(1) << ta.c) - 1;
+            int prev = ta.c - 1;
+            for (int h = 0; h < ta.nhi; h++) {
+                if (ta.hi[h] <= prev || ta.hi[h] >= n) return QSIM_E_ARG;
+                prev = ta.hi[h];
+                m |= uint64_t(1) << ta.hi[h];
+            }
+            if ((m & ta.rest_mask) || ((m | ta.rest_mask) != all) || m != ta.tile_mask) return QSIM_E_ARG;
+            width = ta.t;
+        }
+        if (p.pass_begin[i] > p.pass_begin[i + 1] || p.pass_begin[i + 1] > p.ops.size()) return QSIM_E_ARG;
+        if (p.coef_begin[i] > p.coef_begin[i + 1] || p.coef_begin[i + 1] > p.coefs.size()) return QSIM_E_ARG;
+        if (!pi.strided &&
+            qk::tile_lds_bytes(elem_bytes(dtype), pi.ta.t, p.pass_begin[i + 1] - p.pass_begin[i],
+                               p.coef_begin[i + 1] - p.coef_begin[i]) > qk::max_lds_bytes() - 1024)
+            return QSIM_E_ARG;
+        for (uint32_t j = p.pass_begin[i]; j < p.pass_begin[i + 1]; j++) {
+            const DevOp &o = p.ops[j];
+            if (o.kind != DEVOP_MAT || o.k < 1 || o.k > kMaxK || o.k > width) return QSIM_E_ARG;
+            if (!pi.strided && dtype == QSIM_C128 && o.k > 4) return QSIM_E_ARG;
+            for (int a = 0; a < o.k; a++) {
+                if (o.pos[a] >= width) return QSIM_E_ARG;
+                if (a && o.pos[a] <= o.pos[a - 1]) return QSIM_E_ARG;
+            }
+            const uint32_t d = 1u << o.k;
+            const uint32_t mask = (d >= 32) ? 0xffffffffu : ((1u << d) - 1);
+            if (!o.present || (o.present & ~mask)) return QSIM_E_ARG;
+            const size_t need = size_t(o.coef) + size_t(__builtin_popcount(o.present)) * d;
+            if (need > p.coefs.size()) return QSIM_E_ARG;
+            if (!pi.strided && (o.coef < p.coef_begin[i] || need > p.coef_begin[i + 1])) return QSIM_E_ARG;
+        }
+    }
+    return QSIM_OK;
+}
+
+int compile_circuit(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
+                    const double *params, const qsim_fuse_opts *opt, Compiled *out) {
+    double t0 = now_seconds();
+    FuseConfig fc;
+    PlanConfig pc;
+    default_configs(n, dtype, opt, &fc, &pc);
+    Lowered L;
+    int rc = lower(n, g, ng, mats, params, false, &L);
+    if (rc) return rc;
+    int64_t counts[6];
+    fuse(n, &L, fc, counts);
+    std::vector<uint32_t> present(L.ops.size()), meta(L.ops.size());
+    for (size_t i = 0; i < L.ops.size(); i++) {
+        present[i] = op_present(L.ops[i], fc.sparse);
+        meta[i] = uint32_t(sizeof(DevOp) + size_t(__builtin_popcount(present[i])) *
+                                               L.ops[i].dim() * (1u << L.ops[i].np) * elem_bytes(dtype));
+    }
+    std::vector<Pass> passes;
+    plan_passes(n, L.ops, L.fence_after, meta, pc, &passes);
+    pack_plan(L.ops, present, passes, &out->plan);
+    out->passes.clear();
+    out->passes.reserve(passes.size());
+    for (const Pass &p : passes) {
+        PassInfo pi;
+        pi.strided = p.strided;
+        pi.ta.n = n;
+        pi.ta.t = p.t;
+        pi.ta.c = p.c;
+        pi.ta.nhi = p.nhi;
+        uint64_t all = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
+        pi.ta.rest_mask = all & ~p.tile_mask;
+        pi.ta.tile_mask = p.tile_mask;
+        for (int h = 0; h < p.nhi; h++) pi.ta.hi[h] = uint8_t(p.hi[h]);
+        out->passes.push_back(pi);
+    }
+    qsim_apply_stats &s = out->stats;
+    std::memset(&s, 0, sizeof(s));
+    s.input_gates = L.input_gates;
+    for (int l = 0; l < 6; l++) s.ops_after[l] = counts[l];
+    s.fused_ops = int64_t(L.ops.size());
+    s.passes = int64_t(passes.size());
+    s.terms = out->plan.terms;
+    s.bytes_moved = int64_t(passes.size()) * 2 * (int64_t(1) << n) * int64_t(elem_bytes(dtype));
+    s.tile_qubits = pc.one_op_per_pass ? 0 : pc.tile_qubits;
+    s.max_width = fc.max_width;
+    s.compile_seconds = now_seconds() - t0;
+    return validate_plan(n, dtype, *out);
+}
+
+}  // namespace qs
+
+// ------------------------------------------------------------- handles
+namespace {
+
+int hip_rc(hipError_t e) { return qk::note_hip(e, "runtime call"); }
+
+int grow(void **ptr, size_t *cap, size_t need, hipStream_t st) {
+    if (need <= *cap) return QSIM_OK;
+    if (*ptr) {
+        hipStreamSynchronize(st);
+        hipFree(*ptr);
+        *ptr = nullptr;
+        *cap = 0;
+    }
+    size_t sz = std::max(need, size_t(4096));
+    sz = (sz + sz / 4 + 255) & ~size_t(255);
+    hipError_t e = hipMalloc(ptr, sz);
+    if (e != hipSuccess) { qk::note_hip(e, "hipMalloc"); *ptr = nullptr; return QSIM_E_NOMEM; }
+    *cap = sz;
+    return QSIM_OK;
+}
+
+int grow_host(void **ptr, size_t *cap, size_t need) {
+    if (need <= *cap) return QSIM_OK;
+    if (*ptr) hipHostFree(*ptr);
+    *ptr = nullptr;
+    *cap = 0;
+    size_t sz = std::max(need, size_t(4096));
+    sz = (sz + sz / 4 + 255) & ~size_t(255);
+    hipError_t e = hipHostMalloc(ptr, sz, hipHostMallocDefault);
+    if (e != hipSuccess) { qk::note_hip(e, "hipHostMalloc"); *ptr = nullptr; return QSIM_E_NOMEM; }
+    *cap = sz;
+    return QSIM_OK;
+}
+
+}  // namespace
+
+namespace qs {
+
+// Copy the packed plan to pinned staging (coefficients cast to the state
+// precision) and then to the device, asynchronously on `st`.
+int upload_plan(DeviceTables *dt, int dtype, const PackedPlan &plan, hipStream_t st) {
+    const size_t ops_bytes = plan.ops.size() * sizeof(DevOp);
+    const size_t coef_bytes = plan.coefs.size() * elem_bytes(dtype);
+    const size_t ops_pad = (ops_bytes + 255) & ~size_t(255);
+    if (dt->stage_ev_valid) {
+        hipEventSynchronize(dt->stage_ev);   // previous upload has left the staging buffer
+        dt->stage_ev_valid = false;
+    }
+    int rc = grow_host(&dt->h_stage, &dt->cap_stage, ops_pad + coef_bytes + 256);
+    if (rc) return rc;
+    rc = grow((void **)&dt->d_ops, &dt->cap_ops, ops_pad + 256, st);
+    if (rc) return rc;
+    rc = grow(&dt->d_coefs, &dt->cap_coefs, coef_bytes + 256, st);
+    if (rc) return rc;
+    unsigned char *h = (unsigned char *)dt->h_stage;
+    if (ops_bytes) std::memcpy(h, plan.ops.data(), ops_bytes);
+    if (dtype == QSIM_C64) {
+        float *c = (float *)(h + ops_pad);
+        for (size_t i = 0; i < plan.coefs.size(); i++) {
+            c[2 * i] = float(plan.coefs[i].real());
+            c[2 * i + 1] = float(plan.coefs[i].imag());
+        }
+    } else if (coef_bytes) {
+        std::memcpy(h + ops_pad, plan.coefs.data(), coef_bytes);
+    }
+    if (ops_bytes && hipMemcpyAsync(dt->d_ops, h, ops_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+        return QSIM_E_HIP;
+    if (coef_bytes &&
+        hipMemcpyAsync(dt->d_coefs, h + ops_pad, coef_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+        return QSIM_E_HIP;
+    if (!dt->stage_ev) {
+        if (hipEventCreateWithFlags(&dt->stage_ev, hipEventDisableTiming) != hipSuccess) return QSIM_E_HIP;
+    }
+    if (hipEventRecord(dt->stage_ev, st) != hipSuccess) return QSIM_E_HIP;
+    dt->stage_ev_valid = true;
+    return QSIM_OK;
+}
+
+void free_tables(DeviceTables *dt) {
+    if (dt->stage_ev_valid) hipEventSynchronize(dt->stage_ev);
+    if (dt->stage_ev) hipEventDestroy(dt->stage_ev);
+    if (dt->d_ops) hipFree(dt->d_ops);
+    if (dt->d_coefs) hipFree(dt->d_coefs);
+    if (dt->h_stage) hipHostFree(dt->h_stage);
+    *dt = DeviceTables{};
+}
+
+int enqueue_passes(const Compiled &c, const DeviceTables &dt, int dtype, void *state,
+                   hipStream_t st, bool init_zero_first) {
+    const PackedPlan &p = c.plan;
+    for (size_t i = 0; i < c.passes.size(); i++) {
+        const PassInfo &pi = c.passes[i];
+        const uint32_t ob = p.pass_begin[i], oe = p.pass_begin[i + 1];
+        int rc;
+        if (pi.strided) {
+            for (uint32_t j = ob; j < oe; j++) {
+                rc = qk::launch_sweep(dtype, state, 0, 1, pi.ta.n, p.ops[j], dt.d_coefs, st);
+                if (rc) return rc;
+            }
+        } else {
+            uint32_t flags = (init_zero_first && i == 0) ? qk::TF_INIT_ZERO : 0u;
+            rc = qk::launch_tile(dtype, state, 0, 1, pi.ta, dt.d_ops, ob, oe, dt.d_coefs,
+                                 p.coef_begin[i], p.coef_begin[i + 1], 0, nullptr, flags, st);
+            if (rc) return rc;
+        }
+    }
+    return QSIM_OK;
+}
+
+}  // namespace qs
+
+struct qsim_state {
+    int n = 0;
+    int dtype = 0;
+    void *buf = nullptr;
+    hipStream_t stream = nullptr;
+    DeviceTables tables;
+    void *d_red = nullptr;     // reduction partials and outputs
+    size_t cap_red = 0;
+    void *d_small = nullptr;   // constant coefficients (the X operator)
+    size_t cap_small = 0;
+    void *d_masks = nullptr;   // Pauli masks of qsim_expval
+    size_t cap_masks = 0;
+    double *h_out = nullptr;   // pinned readback
+    size_t cap_out = 0;
+    qsim_apply_stats last{};
+};
+
+struct qsim_program {
+    int n = 0;
+    int dtype = 0;
+    Compiled c;
+    DeviceTables dt;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    void *graph_buf = nullptr;
+    std::vector<hipEvent_t> events;
+    size_t timed_passes = 0;
+};
+
+namespace {
+
+int reduce_buffers(qsim_h h, size_t partial_doubles, size_t out_doubles, double **partials,
+                   double **out) {
+    size_t need = (partial_doubles + out_doubles) * sizeof(double) + 512;
+    int rc = grow(&h->d_red, &h->cap_red, need, h->stream);
+    if (rc) return rc;
+    *partials = (double *)h->d_red;
+    *out = (double *)h->d_red + ((partial_doubles + 31) & ~size_t(31));
+    if (h->cap_out < out_doubles * sizeof(double)) {
+        void *p = h->h_out;
+        size_t cap = h->cap_out;
+        rc = grow_host(&p, &cap, out_doubles * sizeof(double));
+        if (rc) return rc;
+        h->h_out = (double *)p;
+        h->cap_out = cap;
+    }
+    return QSIM_OK;
+}
+
+// Marginal weights of qubits qs (unnormalised), into h->h_out[0 .. 2^nqs).
+int marginal(qsim_h h, const int *qs, int nqs) {
+    const uint32_t nch = qk::marginal_chunks(h->n, nqs);
+    double *part, *out;
+    int rc = reduce_buffers(h, size_t(nch) << nqs, size_t(1) << nqs, &part, &out);
+    if (rc) return rc;
+    rc = qk::launch_marginal(h->dtype, h->buf, 0, 1, h->n, qs, nqs, part, out, h->stream);
+    if (rc) return rc;
+    if (hipMemcpyAsync(h->h_out, out, (size_t(1) << nqs) * sizeof(double), hipMemcpyDeviceToHost,
+                       h->stream) != hipSuccess)
+        return QSIM_E_HIP;
+    return hip_rc(hipStreamSynchronize(h->stream));
+}
+
+int weights01(qsim_h h, int q, double *P0, double *P1) {
+    int rc = marginal(h, &q, 1);
+    if (rc) return rc;
+    *P0 = h->h_out[0];
+    *P1 = h->h_out[1];
+    return QSIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qsim_version(void) { return 1; }
+
+const char *qsim_last_error(void) { return g_last_error; }
+
+const char *qsim_strerror(int s) {
+    switch (s) {
+    case QSIM_OK: return "ok";
+    case QSIM_E_ARG: return "invalid argument";
+    case QSIM_E_QUBIT: return "qubit out of range or repeated";
+    case QSIM_E_NOMEM: return "out of memory";
+    case QSIM_E_ZERO_PROB: return "asserted outcome has zero probability";
+    case QSIM_E_NOT_DEFINITE: return "qubit is not in a definite state";
+    case QSIM_E_HIP: return "HIP runtime error";
+    case QSIM_E_CAPACITY: return "capacity exceeded";
+    case QSIM_E_UNSUPPORTED: return "unsupported gate or option";
+    default: return "unknown status";
+    }
+}
+
+int qsim_create(int n, int dtype, void *dev_buf, size_t buf_bytes, void *hip_stream, qsim_h *out) {
+    if (!out || n < 1 || n > kMaxQubits || (dtype != QSIM_C64 && dtype != QSIM_C128) || !dev_buf)
+        return QSIM_E_ARG;
+    if (buf_bytes < (size_t(1) << n) * elem_bytes(dtype)) return QSIM_E_CAPACITY;
+    int rc = qk::init_kernels();
+    if (rc) return rc;
+    qsim_state *h = new (std::nothrow) qsim_state;
+    if (!h) return QSIM_E_NOMEM;
+    h->n = n;
+    h->dtype = dtype;
+    h->buf = dev_buf;
+    h->stream = (hipStream_t)hip_stream;
+    // constants: the X operator as one XOR-shift-1 diagonal (1, 1)
+    rc = grow(&h->d_small, &h->cap_small, 4096, h->stream);
+    if (rc) { delete h; return rc; }
+    if (dtype == QSIM_C64) {
+        float x[4] = {1, 0, 1, 0};
+        rc = hip_rc(hipMemcpy(h->d_small, x, sizeof(x), hipMemcpyHostToDevice));
+    } else {
+        double x[4] = {1, 0, 1, 0};
+        rc = hip_rc(hipMemcpy(h->d_small, x, sizeof(x), hipMemcpyHostToDevice));
+    }
+    if (!rc) rc = qk::launch_init_zero(dtype, dev_buf, 0, 1, n, h->stream);
+    if (!rc) rc = hip_rc(hipStreamSynchronize(h->stream));
+    if (rc) { qsim_destroy(h); return rc; }
+    *out = h;
+    return QSIM_OK;
+}
+
+int qsim_destroy(qsim_h h) {
+    if (!h) return QSIM_E_ARG;
+    hipStreamSynchronize(h->stream);
+    free_tables(&h->tables);
+    if (h->d_red) hipFree(h->d_red);
+    if (h->d_small) hipFree(h->d_small);
+    if (h->d_masks) hipFree(h->d_masks);
+    if (h->h_out) hipHostFree(h->h_out);
+    delete h;
+    return QSIM_OK;
+}
+
+int qsim_set_stream(qsim_h h, void *st) {
+    if (!h) return QSIM_E_ARG;
+    hipStreamSynchronize(h->stream);
+    h->stream = (hipStream_t)st;
+    return QSIM_OK;
+}
+
+int qsim_init_zero(qsim_h h) {
+    if (!h) return QSIM_E_ARG;
+    return qk::launch_init_zero(h->dtype, h->buf, 0, 1, h->n, h->stream);
+}
+
+int qsim_apply(qsim_h h, const qsim_gate *g, size_t ng, const double *mats, const double *params,
+               const qsim_fuse_opts *opt) {
+    if (!h || (ng && !g)) return QSIM_E_ARG;
+    Compiled c;
+    int rc;
+    try {
+        rc = compile_circuit(h->n, h->dtype, g, ng, mats, params, opt, &c);
+    } catch (const std::bad_alloc &) {
+        return QSIM_E_NOMEM;
+    }
+    if (rc) return rc;
+    if (c.plan.ops.empty()) { h->last = c.stats; return QSIM_OK; }
+    rc = upload_plan(&h->tables, h->dtype, c.plan, h->stream);
+    if (rc) return rc;
+    rc = enqueue_passes(c, h->tables, h->dtype, h->buf, h->stream, false);
+    h->last = c.stats;
+    return rc;
+}
+
+int qsim_compile(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
+                 const double *params, const qsim_fuse_opts *opt, qsim_prog *out) {
+    if (!out || n < 1 || n > kMaxQubits || (dtype != QSIM_C64 && dtype != QSIM_C128) || (ng && !g))
+        return QSIM_E_ARG;
+    int rc = qk::init_kernels();
+    if (rc) return rc;
+    qsim_program *p = new (std::nothrow) qsim_program;
+    if (!p) return QSIM_E_NOMEM;
+    p->n = n;
+    p->dtype = dtype;
+    try {
+        rc = compile_circuit(n, dtype, g, ng, mats, params, opt, &p->c);
+    } catch (const std::bad_alloc &) {
+        rc = QSIM_E_NOMEM;
+    }
+    if (!rc && !p->c.plan.ops.empty()) {
+        rc = upload_plan(&p->dt, dtype, p->c.plan, nullptr);
+        if (!rc) rc = hip_rc(hipStreamSynchronize(nullptr));
+    }
+    if (rc) { qsim_program_destroy(p); return rc; }
+    *out = p;
+    return QSIM_OK;
+}
+
+int qsim_run(qsim_h h, qsim_prog p) {
+    if (!h || !p || h->n != p->n || h->dtype != p->dtype) return QSIM_E_ARG;
+    if (p->c.plan.ops.empty()) return QSIM_OK;
+    if (p->graph_exec && p->graph_buf == h->buf) {
+        return hip_rc(hipGraphLaunch(p->graph_exec, h->stream));
+    }
+    return enqueue_passes(p->c, p->dt, p->dtype, h->buf, h->stream, false);
+}
+
+int qsim_program_graph(qsim_prog p, qsim_h h, int enable) {
+    if (!p || !h || h->n != p->n || h->dtype != p->dtype) return QSIM_E_ARG;
+    if (p->graph_exec) { hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
+    if (p->graph) { hipGraphDestroy(p->graph); p->graph = nullptr; }
+    p->graph_buf = nullptr;
+    if (!enable || p->c.plan.ops.empty()) return QSIM_OK;
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return QSIM_E_HIP;
+    int rc = hip_rc(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    if (!rc) {
+        int erc = enqueue_passes(p->c, p->dt, p->dtype, h->buf, cs, false);
+        hipGraph_t g = nullptr;
+        rc = hip_rc(hipStreamEndCapture(cs, &g));
+        if (!rc && erc) rc = erc;
+        if (!rc) {
+            p->graph = g;
+            rc = hip_rc(hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0));
+        } else if (g) {
+            hipGraphDestroy(g);
+        }
+    }
+    hipStreamDestroy(cs);
+    if (!rc) p->graph_buf = h->buf;
+    return rc;
+}
+
+int qsim_run_timed(qsim_h h, qsim_prog p) {
+    if (!h || !p || h->n != p->n || h->dtype != p->dtype) return QSIM_E_ARG;
+    const size_t np = p->c.passes.size();
+    if (p->events.size() < 2 * np) {
+        for (size_t i = p->events.size(); i < 2 * np; i++) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return QSIM_E_HIP;
+            p->events.push_back(e);
+        }
+    }
+    const PackedPlan &pl = p->c.plan;
+    for (size_t i = 0; i < np; i++) {
+        const PassInfo &pi = p->c.passes[i];
+        if (hipEventRecord(p->events[2 * i], h->stream) != hipSuccess) return QSIM_E_HIP;
+        int rc;
+        if (pi.strided) {
+            rc = QSIM_OK;
+            for (uint32_t j = pl.pass_begin[i]; j < pl.pass_begin[i + 1] && !rc; j++)
+                rc = qk::launch_sweep(p->dtype, h->buf, 0, 1, p->n, pl.ops[j], p->dt.d_coefs, h->stream);
+        } else {
+            rc = qk::launch_tile(p->dtype, h->buf, 0, 1, pi.ta, p->dt.d_ops, pl.pass_begin[i],
+                                 pl.pass_begin[i + 1], p->dt.d_coefs, pl.coef_begin[i],
+                                 pl.coef_begin[i + 1], 0, nullptr, 0, h->stream);
+        }
+        if (rc) return rc;
+        if (hipEventRecord(p->events[2 * i + 1], h->stream) != hipSuccess) return QSIM_E_HIP;
+    }
+    p->timed_passes = np;
+    return QSIM_OK;
+}
+
+int qsim_program_kernel_ms(qsim_prog p, double *ms, int64_t *launches) {
+    if (!p || !ms || !launches) return QSIM_E_ARG;
+    double tot = 0;
+    for (size_t i = 0; i < p->timed_passes; i++) {
+        if (hipEventSynchronize(p->events[2 * i + 1]) != hipSuccess) return QSIM_E_HIP;
+        float f = 0;
+        if (hipEventElapsedTime(&f, p->events[2 * i], p->events[2 * i + 1]) != hipSuccess) return QSIM_E_HIP;
+        tot += f;
+    }
+    *ms = tot;
+    *launches = int64_t(p->timed_passes);
+    return QSIM_OK;
+}
+
+int qsim_program_stats(qsim_prog p, qsim_apply_stats *out) {
+    if (!p || !out) return QSIM_E_ARG;
+    *out = p->c.stats;
+    return QSIM_OK;
+}
+
+int qsim_program_destroy(qsim_prog p) {
+    if (!p) return QSIM_E_ARG;
+    hipDeviceSynchronize();
+    if (p->graph_exec) hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    for (hipEvent_t e : p->events) hipEventDestroy(e);
+    free_tables(&p->dt);
+    delete p;
+    return QSIM_OK;
+}
+
+int qsim_last_stats(qsim_h h, qsim_apply_stats *out) {
+    if (!h || !out) return QSIM_E_ARG;
+    *out = h->last;
+    return QSIM_OK;
+}
+
+int qsim_measure(qsim_h h, int q, double u, int *outcome, double *p_outcome) {
+    if (!h || !outcome || !p_outcome) return QSIM_E_ARG;
+    if (q < 0 || q >= h->n) return QSIM_E_QUBIT;
+    if (!(u >= 0.0 && u < 1.0)) return QSIM_E_ARG;
+    double P0, P1;
+    int rc = weights01(h, q, &P0, &P1);
+    if (rc) return rc;
+    if (!(P0 + P1 > 0.0)) return QSIM_E_ZERO_PROB;
+    const double p0 = P0 / (P0 + P1);
+    const int o = (u < p0) ? 0 : 1;
+    const double kept = o ? P1 : P0;
+    rc = qk::launch_collapse(h->dtype, h->buf, h->n, q, o, 1.0 / std::sqrt(kept), h->stream);
+    if (rc) return rc;
+    *outcome = o;
+    *p_outcome = kept / (P0 + P1);
+    return QSIM_OK;
+}
+
+int qsim_measure_assert(qsim_h h, int q, double *p_zero) {
+    if (!h || !p_zero) return QSIM_E_ARG;
+    if (q < 0 || q >= h->n) return QSIM_E_QUBIT;
+    double P0, P1;
+    int rc = weights01(h, q, &P0, &P1);
+    if (rc) return rc;
+    if (!(P0 > 0.0)) return QSIM_E_ZERO_PROB;
+    rc = qk::launch_collapse(h->dtype, h->buf, h->n, q, 0, 1.0 / std::sqrt(P0), h->stream);
+    if (rc) return rc;
+    *p_zero = P0 / (P0 + P1);
+    return QSIM_OK;
+}
+
+int qsim_reset(qsim_h h, int q) {
+    if (!h) return QSIM_E_ARG;
+    if (q < 0 || q >= h->n) return QSIM_E_QUBIT;
+    double P0, P1;
+    int rc = weights01(h, q, &P0, &P1);
+    if (rc) return rc;
+    if (P1 == 0.0) return QSIM_OK;
+    if (P0 != 0.0) return QSIM_E_NOT_DEFINITE;
+    DevOp x{};
+    x.coef = 0;
+    x.present = 2u;   // shift 1: (X psi)[r] = psi[r ^ 1]
+    x.k = 1;
+    x.pos[0] = uint8_t(q);
+    x.kind = DEVOP_MAT;
+    return qk::launch_sweep(h->dtype, h->buf, 0, 1, h->n, x, h->d_small, h->stream);
+}
+
+int qsim_norm(qsim_h h, double *out) {
+    if (!h || !out) return QSIM_E_ARG;
+    int rc = marginal(h, nullptr, 0);
+    if (rc) return rc;
+    *out = h->h_out[0];
+    return QSIM_OK;
+}
+
+int qsim_probs(qsim_h h, const int *qs, int nqs, double *out) {
+    if (!h || !out || nqs < 0 || nqs > 12 || (nqs && !qs)) return QSIM_E_ARG;
+    for (int i = 0; i < nqs; i++) {
+        if (qs[i] < 0 || qs[i] >= h->n) return QSIM_E_QUBIT;
+        for (int j = 0; j < i; j++)
+            if (qs[j] == qs[i]) return QSIM_E_QUBIT;
+    }
+    int rc = marginal(h, qs, nqs);
+    if (rc) return rc;
+    double tot = 0;
+    for (int j = 0; j < (1 << nqs); j++) tot += h->h_out[j];
+    if (!(tot > 0)) return QSIM_E_ZERO_PROB;
+    for (int j = 0; j < (1 << nqs); j++) out[j] = h->h_out[j] / tot;
+    return QSIM_OK;
+}
+
+int qsim_expval(qsim_h h, const qsim_pauli *t, size_t nt, double *out) {
+    if (!h || !out || (nt && !t)) return QSIM_E_ARG;
+    const uint64_t lim = (h->n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << h->n) - 1);
+    for (size_t k = 0; k < nt; k++) {
+        if ((t[k].xmask & ~lim) || (t[k].zmask & ~lim) || !std::isfinite(t[k].coeff)) return QSIM_E_ARG;
+    }
+    double nrm;
+    int rc = qsim_norm(h, &nrm);
+    if (rc) return rc;
+    if (!(nrm > 0)) return QSIM_E_ZERO_PROB;
+    if (nt == 0) { *out = 0.0; return QSIM_OK; }
+    rc = grow(&h->d_masks, &h->cap_masks, 16 * nt, h->stream);
+    if (rc) return rc;
+    std::vector<uint64_t> masks(2 * nt);
+    for (size_t k = 0; k < nt; k++) { masks[k] = t[k].xmask; masks[nt + k] = t[k].zmask; }
+    uint64_t *dm = (uint64_t *)h->d_masks;
+    if (hipMemcpyAsync(dm, masks.data(), 16 * nt, hipMemcpyHostToDevice, h->stream) != hipSuccess)
+        return QSIM_E_HIP;
+    const uint32_t nch = qk::pauli_chunks(h->n);
+    double *part, *dout;
+    rc = reduce_buffers(h, size_t(nch) * 2 * nt, 2 * nt, &part, &dout);
+    if (rc) return rc;
+    rc = qk::launch_pauli(h->dtype, h->buf, 0, 1, h->n, dm, dm + nt, int(nt), part, dout, h->stream);
+    if (rc) return rc;
+    if (hipMemcpyAsync(h->h_out, dout, 2 * nt * sizeof(double), hipMemcpyDeviceToHost, h->stream) !=
+        hipSuccess)
+        return QSIM_E_HIP;
+    rc = hip_rc(hipStreamSynchronize(h->stream));
+    if (rc) return rc;
+    double total = 0;
+    for (size_t k = 0; k < nt; k++) {
+        const double re = h->h_out[2 * k], im = h->h_out[2 * k + 1];
+        // <P> = Re(i^{#Y} S), S = sum_x (-1)^{popcount(x & z)} conj(a[x ^ x_mask]) a[x]
+        double v;
+        switch (__builtin_popcountll(t[k].xmask & t[k].zmask) & 3) {
+        case 0: v = re; break;
+        case 1: v = -im; break;
+        case 2: v = -re; break;
+        default: v = im; break;
+        }
+        total += t[k].coeff * v;
+    }
+    *out = total / nrm;
+    return QSIM_OK;
+}
+
+int qsim_get_state(qsim_h h, void *dst) {
+    if (!h || !dst) return QSIM_E_ARG;
+    size_t bytes = (size_t(1) << h->n) * elem_bytes(h->dtype);
+    if (hipMemcpyAsync(dst, h->buf, bytes, hipMemcpyDeviceToHost, h->stream) != hipSuccess) return QSIM_E_HIP;
+    return hip_rc(hipStreamSynchronize(h->stream));
+}
+
+int qsim_set_state(qsim_h h, const void *src) {
+    if (!h || !src) return QSIM_E_ARG;
+    size_t bytes = (size_t(1) << h->n) * elem_bytes(h->dtype);
+    if (hipMemcpyAsync(h->buf, src, bytes, hipMemcpyHostToDevice, h->stream) != hipSuccess) return QSIM_E_HIP;
+    return hip_rc(hipStreamSynchronize(h->stream));
+}
+
+int qsim_debug_fuse(int n, const qsim_gate *g, size_t ng, const double *mats, const double *params,
+                    const qsim_fuse_opts *opt, int32_t *out_k, int32_t *out_qubits,
+                    double *out_mats, size_t cap_ops, size_t cap_doubles, size_t *n_ops,
+                    int64_t *counts) {
+    if (n < 1 || n > kMaxQubits || (ng && !g) || !n_ops) return QSIM_E_ARG;
+    FuseConfig fc;
+    PlanConfig pc;
+    default_configs(n, QSIM_C128, opt, &fc, &pc);
+    if (opt && opt->max_width > 0) fc.max_width = std::max(1, std::min(opt->max_width, kMaxK));
+    Lowered L;
+    int rc;
+    int64_t cnt[6];
+    try {
+        rc = lower(n, g, ng, mats, params, false, &L);
+        if (rc) return rc;
+        fuse(n, &L, fc, cnt);
+    } catch (const std::bad_alloc &) {
+        return QSIM_E_NOMEM;
+    }
+    if (counts)
+        for (int l = 0; l < 6; l++) counts[l] = cnt[l];
+    *n_ops = L.ops.size();
+    size_t need = 0;
+    for (const Op &o : L.ops) need += 2 * size_t(o.dim()) * o.dim();
+    if (L.ops.size() > cap_ops || need > cap_doubles) return QSIM_E_CAPACITY;
+    size_t pos = 0;
+    for (size_t i = 0; i < L.ops.size(); i++) {
+        const Op &o = L.ops[i];
+        out_k[i] = o.k;
+        for (int j = 0; j < kMaxK; j++) out_qubits[5 * i + j] = j < o.k ? o.q[j] : -1;
+        for (size_t e = 0; e < size_t(o.dim()) * o.dim(); e++) {
+            out_mats[pos++] = o.m[e].real();
+            out_mats[pos++] = o.m[e].imag();
+        }
+    }
+    return QSIM_OK;
+}
+
+int qsim_debug_plan(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
+                    const double *params, const qsim_fuse_opts *opt, qsim_apply_stats *out) {
+    if (n < 1 || n > kMaxQubits || (dtype != QSIM_C64 && dtype != QSIM_C128) || !out) return QSIM_E_ARG;
+    Compiled c;
+    int rc;
+    try {
+        rc = compile_circuit(n, dtype, g, ng, mats, params, opt, &c);
+    } catch (const std::bad_alloc &) {
+        return QSIM_E_NOMEM;
+    }
+    if (rc) return rc;
+    *out = c.stats;
+    return QSIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+// Internal host-side types of the simulator library: lowered and fused
+// operators, pass plans and the packed device tables.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "qsim.h"
+
+namespace qs {
+
+using cd = std::complex<double>;
+
+constexpr int kMaxK = 5;          // widest operator (2^5 x 2^5)
+constexpr int kMaxQubits = 40;
+
+// A k-qubit operator on ascending qubits q[0] < ... < q[k-1].  The matrix is
+// 2^k x 2^k row-major with local index bit j <-> qubit q[j].
+//
+// Parameterised operators (templates for batched runs) carry `np` angle
+// slots.  Every rotation R_P(theta) = cos(theta/2) I - i sin(theta/2) P is
+// linear in (cos theta/2, sin theta/2), so an operator holding np rotations
+// is a sum over s in {0,1}^np of prod_j (s_j ? sin : cos)(theta_j / 2) times
+// a fixed matrix; `m` then stores the 2^np basis matrices one after another.
+struct Op {
+    int k = 0;
+    int q[kMaxK] = {0, 0, 0, 0, 0};
+    int np = 0;                 // number of angle slots
+    int slot[3] = {-1, -1, -1}; // parameter-vector indices
+    std::vector<cd> m;          // (1 << np) * 4^k entries
+    int src_kind = -1;          // originating gate kind for unfused ops
+    int orient = 0;             // 2-qubit gates: 1 if the record named the pair descending
+    bool dead = false;
+
+    int dim() const { return 1 << k; }
+    uint64_t mask() const {
+        uint64_t r = 0;
+        for (int j = 0; j < k; j++) r |= uint64_t(1) << q[j];
+        return r;
+    }
+};
+
+// Circuit element after lowering: an operator, or a fence.
+struct Lowered {
+    std::vector<Op> ops;
+    std::vector<int> fence_after;   // op indices after which a barrier sits
+    int64_t input_gates = 0;
+};
+
+struct FuseConfig {
+    int level = 5;
+    int max_width = 4;
+    double lds_cost = 3.0;     // cost of one extra operator, in complex MACs per amplitude
+    int max_params = 2;        // angle slots per fused operator (templates)
+    bool sparse = true;
+};
+
+// ---- lowering (gates.cpp)
+// Returns QSIM_OK or an error; fills `out`.  Gate matrices are built in FP64.
+int lower(int n, const qsim_gate *g, size_t ng, const double *mats,
+          const double *params, bool keep_params, Lowered *out);
+// Dense matrix of one gate record on its own qubits in record order.
+int gate_matrix(const qsim_gate &g, const double *theta, std::vector<cd> *m);
+
+// ---- fusion (fuse.cpp)
+// Applies the fusion levels in place; counts[l] = operator count after
+// level l (for l <= cfg.level).
+void fuse(int n, Lowered *L, const FuseConfig &cfg, int64_t counts[6]);
+// Helpers shared by fusion and packing.
+void embed(const Op &a, const int *uq, int uk, std::vector<cd> *out, int basis);
+int xor_terms(const cd *m, int k, double tol, uint32_t *present);
+double max_abs(const cd *m, size_t n);
+
+// ---- planning (plan.cpp)
+struct Pass {
+    int t = 0;                    // tile qubits
+    int c = 0;                    // contiguous low qubits (0..c-1) in the tile
+    uint64_t tile_mask = 0;       // all tile qubits
+    int nhi = 0;
+    int hi[kMaxQubits] = {0};     // tile qubits >= c, ascending
+    std::vector<int> ops;         // operator indices (into the fused list)
+    bool strided = false;         // one operator applied by the strided sweep
+};
+
+struct PlanConfig {
+    int tile_qubits = 12;
+    int low_qubits = 3;
+    int window = 1024;            // lookahead when filling a pass
+    int max_tile_k = 5;           // widest operator the tile kernel applies
+    size_t meta_budget = 16384;   // LDS bytes for a pass's operator records and coefficients
+    bool one_op_per_pass = false;
+};
+
+// meta_bytes[i]: LDS bytes operator i needs in a tiled pass (record +
+// coefficients at the state precision).
+void plan_passes(int n, const std::vector<Op> &ops, const std::vector<int> &fence_after,
+                 const std::vector<uint32_t> &meta_bytes, const PlanConfig &cfg,
+                 std::vector<Pass> *passes);
+
+// ---- packing into device tables (plan.cpp)
+// Device operator record (16 bytes): see kernels.hip.
+struct DevOp {
+    uint32_t coef;     // offset of the first term's coefficients (complex elements)
+    uint32_t present;  // bit m set: the XOR-shift-m diagonal is nonzero
+    uint8_t k;
+    uint8_t pos[5];    // qubit positions (tile-local for tiled passes, global for strided)
+    uint8_t kind;      // DEVOP_*
+    uint8_t pad;
+};
+static_assert(sizeof(DevOp) == 16, "DevOp layout");
+
+enum { DEVOP_MAT = 0, DEVOP_MEASURE = 1, DEVOP_ASSERT0 = 2, DEVOP_RESET = 3 };
+
+struct PackedPlan {
+    std::vector<DevOp> ops;             // in pass order
+    std::vector<uint32_t> pass_begin;   // op range of pass i: [pass_begin[i], pass_begin[i+1])
+    std::vector<uint32_t> coef_begin;   // coefficient range of pass i, likewise
+    std::vector<cd> coefs;              // FP64 coefficients; cast on upload
+    int64_t terms = 0;
+};
+
+// Shifts m whose XOR diagonal M[r][r ^ m] is nonzero in some basis block
+// (all shifts when `sparse` is false).
+uint32_t op_present(const Op &o, bool sparse);
+
+// Pack fused ops into device records following `passes`.  For
+// parameterised ops the coefficient layout holds the 2^np basis blocks
+// (a bind step combines them).
+void pack_plan(const std::vector<Op> &ops, const std::vector<uint32_t> &present,
+               const std::vector<Pass> &passes, PackedPlan *out);
+
+double now_seconds();
+
+}  // namespace qs

@@ -1,0 +1,664 @@
+// gfx950 kernels of the state-vector simulator.
+//
+// State layout: 2^n interleaved complex amplitudes (complex64 or complex128),
+// amplitude index i = sum_q b_q 2^q (Section 3.2).  Batches place states
+// `sstride` elements apart.
+//
+// Operators.  A fused k-qubit operator M (2^k x 2^k) is stored by its XOR-
+// shift diagonals: M[r][r ^ m] for the shifts m whose diagonal is nonzero
+// (bit m of `present`), so that the group update of Eq. (1q-op)/(2q-op),
+// generalised to k qubits, reads
+//     y[r] = sum_{m present} d_m[r] * x[r ^ m].
+// A dense operator has all 2^k shifts; a Pauli-string exponential has two
+// (m = 0 and m = its X/Y mask); diagonal gates one.  The shift loop is
+// unrolled at compile time and the test of `present` is wave-uniform, so an
+// absent diagonal costs a scalar branch and no vector work.
+//
+// Reductions (probabilities, norms, Pauli overlaps) accumulate in FP64 with a
+// fixed order: per-thread sequential sums, a butterfly within the wave read
+// from lane 0, wave partials summed in index order, then chunk partials
+// summed in index order by a finishing kernel.  No floating-point atomics, so
+// results are bit-identical from run to run.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "launch.h"
+
+namespace qk {
+
+using qs::DevOp;
+
+constexpr int NT = 256;            // threads per workgroup (4 waves of 64)
+constexpr int NWAVES = NT / 64;
+
+template <typename T>
+struct alignas(2 * sizeof(T)) Cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ void cmac(Cx<T> &acc, const Cx<T> c, const Cx<T> x) {
+    acc.re = fma(c.re, x.re, acc.re);
+    acc.re = fma(-c.im, x.im, acc.re);
+    acc.im = fma(c.re, x.im, acc.im);
+    acc.im = fma(c.im, x.re, acc.im);
+}
+
+// y[r] = sum over present shifts m of d_m[r] * x[r ^ m]; cf holds the present
+// diagonals in ascending m, 2^K entries each.
+template <typename T, int K>
+__device__ __forceinline__ void apply_group(const Cx<T> (&x)[1 << K], Cx<T> (&y)[1 << K],
+                                            uint32_t present, const Cx<T> *__restrict__ cf) {
+    constexpr int D = 1 << K;
+#pragma unroll
+    for (int r = 0; r < D; r++) y[r] = Cx<T>{T(0), T(0)};
+    int ti = 0;
+#pragma unroll
+    for (int m = 0; m < D; m++) {
+        if (present & (1u << m)) {
+            const Cx<T> *c = cf + ti * D;
+#pragma unroll
+            for (int r = 0; r < D; r++) cmac(y[r], c[r], x[r ^ m]);
+            ti++;
+        }
+    }
+}
+
+// ------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum of `v` over the workgroup, identical on every thread, fixed order.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+    __shared__ double red[NV][NWAVES];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        double s = wave_sum(v[i]);
+        if (lane == 0) red[i][w] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        double s = 0;
+#pragma unroll
+        for (int j = 0; j < NWAVES; j++) s += red[i][j];
+        v[i] = s;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ double norm2(const Cx<T> a) {
+    const double re = double(a.re), im = double(a.im);
+    return re * re + im * im;
+}
+
+// LDS bank swizzle of tile element j: the low bits of j are XORed with a fold
+// of its higher bits, so that the power-of-two strides of a group's members
+// spread over the banks.  A bijection on [0, 2^t).  16-byte elements (complex
+// double) fold 3 bits, 8-byte elements fold 4.
+#ifndef QSIM_LDS_SWIZZLE
+#define QSIM_LDS_SWIZZLE 1
+#endif
+template <typename T>
+__device__ __forceinline__ int sw(int j) {
+#if QSIM_LDS_SWIZZLE
+    if constexpr (sizeof(T) == 8) return j ^ (((j >> 3) ^ (j >> 6) ^ (j >> 9) ^ (j >> 12)) & 7);
+    else return j ^ (((j >> 4) ^ (j >> 8) ^ (j >> 12)) & 15);
+#else
+    return j;
+#endif
+}
+
+// ------------------------------------------------------------ tile kernel
+// Operator record fields, read as one scalar dword quad (see qs::DevOp).
+struct OpRec {
+    uint32_t coef, present;
+    int k, kind;
+    int pos[5];
+};
+
+__device__ __forceinline__ OpRec decode_op(uint4 w) {
+    w.x = __builtin_amdgcn_readfirstlane(w.x);
+    w.y = __builtin_amdgcn_readfirstlane(w.y);
+    w.z = __builtin_amdgcn_readfirstlane(w.z);
+    w.w = __builtin_amdgcn_readfirstlane(w.w);
+    OpRec o;
+    o.coef = w.x;
+    o.present = w.y;
+    o.k = int(w.z & 0xff);
+    o.pos[0] = int((w.z >> 8) & 0xff);
+    o.pos[1] = int((w.z >> 16) & 0xff);
+    o.pos[2] = int(w.z >> 24);
+    o.pos[3] = int(w.w & 0xff);
+    o.pos[4] = int((w.w >> 8) & 0xff);
+    o.kind = int((w.w >> 16) & 0xff);
+    return o;
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void apply_lds(Cx<T> *__restrict__ s, int t, const OpRec &op,
+                                          const Cx<T> *__restrict__ cf) {
+    constexpr int D = 1 << K;
+    int p[K];
+#pragma unroll
+    for (int j = 0; j < K; j++) p[j] = op.pos[j];
+    int off[D];
+    off[0] = 0;
+#pragma unroll
+    for (int r = 1; r < D; r++) off[r] = off[r & (r - 1)] + (1 << p[__builtin_ctz(r)]);
+    const int ngroups = 1 << (t - K);
+    for (int g = threadIdx.x; g < ngroups; g += NT) {
+        int base = g;
+#pragma unroll
+        for (int j = 0; j < K; j++) base = ((base >> p[j]) << (p[j] + 1)) | (base & ((1 << p[j]) - 1));
+        Cx<T> x[D], y[D];
+#pragma unroll
+        for (int r = 0; r < D; r++) x[r] = s[sw<T>(base + off[r])];
+        apply_group<T, K>(x, y, op.present, cf);
+#pragma unroll
+        for (int r = 0; r < D; r++) s[sw<T>(base + off[r])] = y[r];
+    }
+}
+
+// The b-th lowest set bit of m, as a one-bit mask (0 if m has fewer bits).
+__device__ __forceinline__ uint64_t nth_bit(uint64_t m, int b) {
+    for (int i = 0; i < b && m; i++) m &= m - 1;
+    return m & (~m + 1);
+}
+
+// Scatter the low bits of x into the set bits of m, in ascending order.
+__device__ __forceinline__ uint64_t deposit(uint64_t x, uint64_t m) {
+    uint64_t r = 0;
+    while (m && x) {
+        const uint64_t lo = m & (~m + 1);
+        if (x & 1) r |= lo;
+        x >>= 1;
+        m &= m - 1;
+    }
+    return r;
+}
+
+// Measurement, assertion and reset inside a resident program (t == n, so the
+// LDS index is the amplitude index).  Returns 0 or a negative status.
+template <typename T>
+__device__ int lds_measure(Cx<T> *__restrict__ s, int t, const OpRec &op, const MeasArgs &ma,
+                           uint32_t b) {
+    const int q = op.pos[0];
+    const int slot = int(op.coef);
+    const int TN = 1 << t;
+    double w[2] = {0.0, 0.0};
+    for (int j = threadIdx.x; j < TN; j += NT) w[(j >> q) & 1] += norm2(s[sw<T>(j)]);
+    block_sum<2>(w);
+    const double P0 = w[0], P1 = w[1];
+    if (op.kind == qs::DEVOP_RESET) {
+        if (P1 == 0.0) return 0;
+        if (P0 != 0.0) return QSIM_E_NOT_DEFINITE;
+        const int half = TN >> 1;
+        for (int g = threadIdx.x; g < half; g += NT) {
+            const int lo = ((g >> q) << (q + 1)) | (g & ((1 << q) - 1));
+            s[sw<T>(lo)] = s[sw<T>(lo | (1 << q))];
+            s[sw<T>(lo | (1 << q))] = Cx<T>{T(0), T(0)};
+        }
+        return 0;
+    }
+    int o;
+    const size_t idx = size_t(b) * ma.nslots + slot;
+    if (op.kind == qs::DEVOP_ASSERT0) {
+        if (!(P0 > 0.0)) return QSIM_E_ZERO_PROB;
+        o = 0;
+    } else if (ma.forced && ma.forced[idx] >= 0) {
+        o = ma.forced[idx];
+        if (!((o ? P1 : P0) > 0.0)) return QSIM_E_ZERO_PROB;
+    } else {
+        const double p0 = P0 / (P0 + P1);
+        o = (ma.uniforms[idx] < p0) ? 0 : 1;
+    }
+    const double kept = o ? P1 : P0;
+    const T scale = T(1.0 / sqrt(kept));
+    if (threadIdx.x == 0) {
+        ma.outcomes[idx] = o;
+        ma.probs[idx] = kept / (P0 + P1);
+    }
+    for (int j = threadIdx.x; j < TN; j += NT) {
+        Cx<T> a = s[sw<T>(j)];
+        if (((j >> q) & 1) == o) { a.re *= scale; a.im *= scale; }
+        else a = Cx<T>{T(0), T(0)};
+        s[sw<T>(j)] = a;
+    }
+    return 0;
+}
+
+// One tile of 2^t amplitudes per workgroup (blockIdx.x: tile, blockIdx.y:
+// state of a batch).  Element j of the tile (j = tid + i * NT, E = 2^LE
+// elements per thread) lives at amplitude  base | deposit(j, tile_mask),
+// where base deposits the tile index into the other qubits.
+//
+// The pass's operator records and coefficients ([ob, oe) and [cb, ce)) are
+// copied into LDS behind the tile, so that no operator waits on a global
+// load; their loads and the E tile loads per thread are all issued before
+// the first LDS write.
+template <typename T, int LE>
+__global__ void __launch_bounds__(NT) k_tile(Cx<T> *__restrict__ state, uint64_t sstride,
+                                             TileArgs ta, const uint4 *__restrict__ ops,
+                                             uint32_t ob, uint32_t oe,
+                                             const Cx<T> *__restrict__ coefs, uint32_t cb,
+                                             uint32_t ce, uint64_t cstride, MeasArgs ma,
+                                             uint32_t flags) {
+    constexpr int E = 1 << LE;
+    extern __shared__ __align__(16) unsigned char smem[];
+    Cx<T> *s = reinterpret_cast<Cx<T> *>(smem);
+    const int TN = 1 << ta.t;
+    uint4 *lops = reinterpret_cast<uint4 *>(smem + size_t(TN) * sizeof(Cx<T>));
+    Cx<T> *lcf = reinterpret_cast<Cx<T> *>(lops + (oe - ob));
+    const uint32_t b = blockIdx.y;
+    Cx<T> *st = state + size_t(b) * sstride;
+    const Cx<T> *cfg = coefs + size_t(b) * cstride + cb;
+    const int tid = threadIdx.x;
+    const bool active = (E > 1) || (tid < TN);
+
+    // operator records and coefficients of the pass: first into registers
+    constexpr int MR = 4;   // records / coefficients per thread held across the tile loads
+    const int nrec = int(oe - ob), ncf = int(ce - cb);
+    uint4 rr[MR];
+    Cx<T> cr[MR];
+#pragma unroll
+    for (int m = 0; m < MR; m++) {
+        const int x = tid + m * NT;
+        if (x < nrec) rr[m] = ops[ob + x];
+        if (x < ncf) cr[m] = cfg[x];
+    }
+
+    const uint64_t base = deposit(blockIdx.x, ta.rest_mask);
+    // thread part: the 8 low bits of j; iteration part: the bits above
+    uint64_t toff = 0;
+#pragma unroll
+    for (int bt = 0; bt < 8; bt++)
+        if ((tid >> bt) & 1) toff |= nth_bit(ta.tile_mask, bt);
+    uint64_t ibit[LE > 0 ? LE : 1];
+#pragma unroll
+    for (int bt = 0; bt < LE; bt++) ibit[bt] = nth_bit(ta.tile_mask, 8 + bt);
+
+    Cx<T> v[E];
+    if (!(flags & TF_INIT_ZERO)) {
+#pragma unroll
+        for (int i = 0; i < E; i++) {
+            uint64_t io = 0;
+#pragma unroll
+            for (int bt = 0; bt < LE; bt++)
+                if ((i >> bt) & 1) io |= ibit[bt];
+            if (active) v[i] = st[base | toff | io];
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < MR; m++) {
+        const int x = tid + m * NT;
+        if (x < nrec) lops[x] = rr[m];
+        if (x < ncf) lcf[x] = cr[m];
+    }
+    for (int x = tid + MR * NT; x < nrec; x += NT) lops[x] = ops[ob + x];
+    for (int x = tid + MR * NT; x < ncf; x += NT) lcf[x] = cfg[x];
+    if (flags & TF_INIT_ZERO) {
+#pragma unroll
+        for (int i = 0; i < E; i++)
+            if (active) s[sw<T>(tid + i * NT)] = Cx<T>{T((base == 0 && tid == 0 && i == 0) ? 1 : 0), T(0)};
+    } else {
+#pragma unroll
+        for (int i = 0; i < E; i++)
+            if (active) s[sw<T>(tid + i * NT)] = v[i];
+    }
+    __syncthreads();
+
+    int status = 0;
+    int i = 0;
+    for (; i < nrec; i++) {
+        const OpRec op = decode_op(lops[i]);
+        if (op.kind == qs::DEVOP_MAT) {
+            const Cx<T> *cf = lcf + (op.coef - cb);
+            switch (op.k) {
+            case 1: apply_lds<T, 1>(s, ta.t, op, cf); break;
+            case 2: apply_lds<T, 2>(s, ta.t, op, cf); break;
+            case 3: apply_lds<T, 3>(s, ta.t, op, cf); break;
+            case 4: apply_lds<T, 4>(s, ta.t, op, cf); break;
+            default:
+                if constexpr (sizeof(T) == 4) apply_lds<T, 5>(s, ta.t, op, cf);
+                break;
+            }
+        } else {
+            status = lds_measure<T>(s, ta.t, op, ma, b);
+        }
+        __syncthreads();
+        if (status) break;
+    }
+    if (ma.status && tid == 0) {
+        ma.status[b] = status;
+        if (ma.fail_at) ma.fail_at[b] = status ? int(ob) + i : -1;
+    }
+    if (!(flags & TF_NO_STORE)) {
+#pragma unroll
+        for (int i2 = 0; i2 < E; i2++)
+            if (active) v[i2] = s[sw<T>(tid + i2 * NT)];
+#pragma unroll
+        for (int i2 = 0; i2 < E; i2++) {
+            uint64_t io = 0;
+#pragma unroll
+            for (int bt = 0; bt < LE; bt++)
+                if ((i2 >> bt) & 1) io |= ibit[bt];
+            if (active) st[base | toff | io] = v[i2];
+        }
+    }
+}
+
+// --------------------------------------------------------- strided sweep
+template <typename T, int K>
+__global__ void __launch_bounds__(NT) k_sweep(Cx<T> *__restrict__ state, uint64_t sstride, int n,
+                                              DevOp op, const Cx<T> *__restrict__ cf) {
+    constexpr int D = 1 << K;
+    Cx<T> *st = state + size_t(blockIdx.y) * sstride;
+    int p[K];
+#pragma unroll
+    for (int j = 0; j < K; j++) p[j] = op.pos[j];
+    uint64_t off[D];
+    off[0] = 0;
+#pragma unroll
+    for (int r = 1; r < D; r++) off[r] = off[r & (r - 1)] + (uint64_t(1) << p[__builtin_ctz(r)]);
+    const uint64_t ngroups = uint64_t(1) << (n - K);
+    for (uint64_t g = uint64_t(blockIdx.x) * NT + threadIdx.x; g < ngroups;
+         g += uint64_t(gridDim.x) * NT) {
+        uint64_t base = g;
+#pragma unroll
+        for (int j = 0; j < K; j++)
+            base = ((base >> p[j]) << (p[j] + 1)) | (base & ((uint64_t(1) << p[j]) - 1));
+        Cx<T> x[D], y[D];
+#pragma unroll
+        for (int r = 0; r < D; r++) x[r] = st[base + off[r]];
+        apply_group<T, K>(x, y, op.present, cf + op.coef);
+#pragma unroll
+        for (int r = 0; r < D; r++) st[base + off[r]] = y[r];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_init_zero(Cx<T> *__restrict__ state, uint64_t sstride,
+                                                  uint64_t len) {
+    Cx<T> *st = state + size_t(blockIdx.y) * sstride;
+    for (uint64_t i = uint64_t(blockIdx.x) * NT + threadIdx.x; i < len; i += uint64_t(gridDim.x) * NT)
+        st[i] = Cx<T>{T(i == 0 ? 1 : 0), T(0)};
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_collapse(Cx<T> *__restrict__ state, uint64_t len, int q,
+                                                 int outcome, T scale) {
+    for (uint64_t i = uint64_t(blockIdx.x) * NT + threadIdx.x; i < len; i += uint64_t(gridDim.x) * NT) {
+        Cx<T> a = state[i];
+        if (int((i >> q) & 1) == outcome) { a.re *= scale; a.im *= scale; }
+        else a = Cx<T>{T(0), T(0)};
+        state[i] = a;
+    }
+}
+
+// ---------------------------------------------------------- reductions
+struct MargArgs {
+    int32_t n, nqs;
+    int32_t sorted[12];   // qubits of the marginal, ascending (for zero insertion)
+    int32_t qs[12];       // qubits in output-bit order
+};
+
+// partials[((b * nbins) + bin) * nchunks + chunk]
+template <typename T>
+__global__ void __launch_bounds__(NT) k_marginal(const Cx<T> *__restrict__ state, uint64_t sstride,
+                                                 MargArgs a, double *__restrict__ partials) {
+    const Cx<T> *st = state + size_t(blockIdx.z) * sstride;
+    const uint32_t bin = blockIdx.y, chunk = blockIdx.x, nchunks = gridDim.x;
+    const uint64_t R = uint64_t(1) << (a.n - a.nqs);
+    const uint64_t per = R / nchunks;
+    uint64_t binbits = 0;
+    for (int i = 0; i < a.nqs; i++)
+        if ((bin >> i) & 1) binbits |= uint64_t(1) << a.qs[i];
+    double acc[1] = {0.0};
+    for (uint64_t r = uint64_t(chunk) * per + threadIdx.x; r < uint64_t(chunk + 1) * per; r += NT) {
+        uint64_t x = r;
+        for (int i = 0; i < a.nqs; i++) {
+            const int p = a.sorted[i];
+            x = ((x >> p) << (p + 1)) | (x & ((uint64_t(1) << p) - 1));
+        }
+        acc[0] += norm2(st[x | binbits]);
+    }
+    block_sum<1>(acc);
+    if (threadIdx.x == 0)
+        partials[(size_t(blockIdx.z) * gridDim.y + bin) * nchunks + chunk] = acc[0];
+}
+
+// partials[((b * nterms + k) * 2 + comp) * nchunks + chunk]
+template <typename T>
+__global__ void __launch_bounds__(NT) k_pauli(const Cx<T> *__restrict__ state, uint64_t sstride,
+                                              int n, const uint64_t *__restrict__ xmask,
+                                              const uint64_t *__restrict__ zmask,
+                                              double *__restrict__ partials) {
+    const Cx<T> *st = state + size_t(blockIdx.z) * sstride;
+    const uint32_t k = blockIdx.y, chunk = blockIdx.x, nchunks = gridDim.x;
+    const uint64_t xm = xmask[k], zm = zmask[k];
+    const uint64_t per = (uint64_t(1) << n) / nchunks;
+    double acc[2] = {0.0, 0.0};
+    for (uint64_t x = uint64_t(chunk) * per + threadIdx.x; x < uint64_t(chunk + 1) * per; x += NT) {
+        const Cx<T> a = st[x], c = st[x ^ xm];
+        const double ar = double(a.re), ai = double(a.im), cr = double(c.re), ci = double(c.im);
+        // conj(c) * a
+        double re = cr * ar + ci * ai, im = cr * ai - ci * ar;
+        if (__builtin_popcountll(x & zm) & 1) { re = -re; im = -im; }
+        acc[0] += re;
+        acc[1] += im;
+    }
+    block_sum<2>(acc);
+    if (threadIdx.x == 0) {
+        const size_t o = (size_t(blockIdx.z) * gridDim.y + k) * 2;
+        partials[(o + 0) * nchunks + chunk] = acc[0];
+        partials[(o + 1) * nchunks + chunk] = acc[1];
+    }
+}
+
+// out[i] = sum_{c < nchunks} partials[i * nchunks + c], in index order.
+__global__ void __launch_bounds__(NT) k_finish(const double *__restrict__ partials, uint32_t nchunks,
+                                               double *__restrict__ out) {
+    const double *p = partials + size_t(blockIdx.x) * nchunks;
+    double acc[1] = {0.0};
+    for (uint32_t c = threadIdx.x; c < nchunks; c += NT) acc[0] += p[c];
+    block_sum<1>(acc);
+    if (threadIdx.x == 0) out[blockIdx.x] = acc[0];
+}
+
+// ------------------------------------------------------------- launchers
+namespace {
+int check(hipError_t e) { return note_hip(e, "kernel launch"); }
+
+uint32_t grid_for(uint64_t work) {
+    uint64_t g = (work + NT - 1) / NT;
+    if (g > 65536) g = 65536;
+    return uint32_t(g ? g : 1);
+}
+}  // namespace
+
+size_t max_lds_bytes() { return 160 * 1024; }
+
+template <typename T, int LE>
+static void lds_attr() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<T, LE>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(max_lds_bytes()));
+    if (e != hipSuccess) note_hip(e, "hipFuncSetAttribute(k_tile)");
+}
+
+int init_kernels() {
+    static int done = 0;
+    if (done) return QSIM_OK;
+    // Allow the tile kernels the largest dynamic LDS they use (160 KiB).  The
+    // attribute is advisory on this platform: a refusal is recorded, and a
+    // launch that then asks for too much LDS reports its own error.
+    lds_attr<float, 0>();
+    lds_attr<float, 1>();
+    lds_attr<float, 2>();
+    lds_attr<float, 3>();
+    lds_attr<float, 4>();
+    lds_attr<float, 5>();
+    lds_attr<float, 6>();
+    lds_attr<double, 0>();
+    lds_attr<double, 1>();
+    lds_attr<double, 2>();
+    lds_attr<double, 3>();
+    lds_attr<double, 4>();
+    lds_attr<double, 5>();
+    (void)hipGetLastError();
+    done = 1;
+    return QSIM_OK;
+}
+
+template <typename T, int LE>
+static void tile_t(void *state, uint64_t sstride, uint32_t nstates, const TileArgs &ta,
+                   const DevOp *ops, uint32_t ob, uint32_t oe, const void *coefs, uint32_t cb,
+                   uint32_t ce, uint64_t cstride, const MeasArgs &m, uint32_t flags,
+                   hipStream_t st) {
+    const dim3 grid(uint32_t(uint64_t(1) << (ta.n - ta.t)), nstates);
+    const size_t lds = tile_lds_bytes(sizeof(Cx<T>), ta.t, oe - ob, ce - cb);
+    hipLaunchKernelGGL((k_tile<T, LE>), grid, dim3(NT), lds, st, (Cx<T> *)state, sstride, ta,
+                       (const uint4 *)ops, ob, oe, (const Cx<T> *)coefs, cb, ce, cstride, m, flags);
+}
+
+template <typename T>
+static int tile_dispatch(void *state, uint64_t sstride, uint32_t nstates, const TileArgs &ta,
+                         const DevOp *ops, uint32_t ob, uint32_t oe, const void *coefs,
+                         uint32_t cb, uint32_t ce, uint64_t cstride, const MeasArgs &m,
+                         uint32_t flags, hipStream_t st) {
+    const int le = ta.t > 8 ? ta.t - 8 : 0;
+    switch (le) {
+    case 0: tile_t<T, 0>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st); break;
+    case 1: tile_t<T, 1>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st); break;
+    case 2: tile_t<T, 2>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st); break;
+    case 3: tile_t<T, 3>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st); break;
+    case 4: tile_t<T, 4>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st); break;
+    case 5: tile_t<T, 5>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st); break;
+    case 6: tile_t<T, 6>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st); break;
+    default: return QSIM_E_ARG;
+    }
+    return QSIM_OK;
+}
+
+size_t tile_lds_bytes(size_t elem, int t, uint32_t nops, uint32_t ncoefs) {
+    return (size_t(1) << t) * elem + size_t(nops) * 16 + size_t(ncoefs) * elem;
+}
+
+int launch_tile(int dtype, void *state, uint64_t sstride, uint32_t nstates, const TileArgs &ta,
+                const DevOp *ops, uint32_t ob, uint32_t oe, const void *coefs, uint32_t cb,
+                uint32_t ce, uint64_t cstride, const MeasArgs *ma, uint32_t flags,
+                hipStream_t st) {
+    MeasArgs m{};
+    if (ma) m = *ma;
+    if (ta.t < 1 || ta.t > 14 || ta.t > ta.n || ce < cb || oe < ob) return QSIM_E_ARG;
+    if (tile_lds_bytes(dtype == QSIM_C64 ? 8 : 16, ta.t, oe - ob, ce - cb) > max_lds_bytes())
+        return QSIM_E_CAPACITY;
+    int rc = (dtype == QSIM_C64)
+                 ? tile_dispatch<float>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st)
+                 : tile_dispatch<double>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st);
+    if (rc) return rc;
+    return check(hipGetLastError());
+}
+
+template <typename T>
+static void sweep_t(Cx<T> *state, uint64_t sstride, uint32_t nstates, int n, const DevOp &op,
+                    const Cx<T> *cf, hipStream_t st) {
+    const dim3 grid(grid_for(uint64_t(1) << (n - op.k)), nstates);
+    switch (op.k) {
+    case 1: hipLaunchKernelGGL((k_sweep<T, 1>), grid, dim3(NT), 0, st, state, sstride, n, op, cf); break;
+    case 2: hipLaunchKernelGGL((k_sweep<T, 2>), grid, dim3(NT), 0, st, state, sstride, n, op, cf); break;
+    case 3: hipLaunchKernelGGL((k_sweep<T, 3>), grid, dim3(NT), 0, st, state, sstride, n, op, cf); break;
+    case 4: hipLaunchKernelGGL((k_sweep<T, 4>), grid, dim3(NT), 0, st, state, sstride, n, op, cf); break;
+    default: hipLaunchKernelGGL((k_sweep<T, 5>), grid, dim3(NT), 0, st, state, sstride, n, op, cf); break;
+    }
+}
+
+int launch_sweep(int dtype, void *state, uint64_t sstride, uint32_t nstates, int n,
+                 const DevOp &op, const void *coefs, hipStream_t st) {
+    if (op.k < 1 || op.k > 5 || op.k > n) return QSIM_E_ARG;
+    if (dtype == QSIM_C64)
+        sweep_t<float>((Cx<float> *)state, sstride, nstates, n, op, (const Cx<float> *)coefs, st);
+    else
+        sweep_t<double>((Cx<double> *)state, sstride, nstates, n, op, (const Cx<double> *)coefs, st);
+    return check(hipGetLastError());
+}
+
+int launch_init_zero(int dtype, void *state, uint64_t sstride, uint32_t nstates, int n,
+                     hipStream_t st) {
+    const uint64_t len = uint64_t(1) << n;
+    const dim3 grid(grid_for(len), nstates);
+    if (dtype == QSIM_C64)
+        hipLaunchKernelGGL(k_init_zero<float>, grid, dim3(NT), 0, st, (Cx<float> *)state, sstride, len);
+    else
+        hipLaunchKernelGGL(k_init_zero<double>, grid, dim3(NT), 0, st, (Cx<double> *)state, sstride, len);
+    return check(hipGetLastError());
+}
+
+uint32_t marginal_chunks(int n, int nqs) {
+    const uint64_t R = uint64_t(1) << (n - nqs);
+    uint64_t c = R / 4096;
+    if (c < 1) c = 1;
+    if (c > 512) c = 512;
+    return uint32_t(c);
+}
+
+int launch_marginal(int dtype, const void *state, uint64_t sstride, uint32_t nstates, int n,
+                    const int *qs, int nqs, double *partials, double *out, hipStream_t st) {
+    if (nqs < 0 || nqs > 12 || nqs > n) return QSIM_E_ARG;
+    MargArgs a{};
+    a.n = n;
+    a.nqs = nqs;
+    for (int i = 0; i < nqs; i++) a.qs[i] = a.sorted[i] = qs[i];
+    for (int i = 0; i < nqs; i++)
+        for (int j = i + 1; j < nqs; j++)
+            if (a.sorted[j] < a.sorted[i]) { int t = a.sorted[i]; a.sorted[i] = a.sorted[j]; a.sorted[j] = t; }
+    const uint32_t nchunks = marginal_chunks(n, nqs);
+    const dim3 grid(nchunks, 1u << nqs, nstates);
+    if (dtype == QSIM_C64)
+        hipLaunchKernelGGL(k_marginal<float>, grid, dim3(NT), 0, st, (const Cx<float> *)state, sstride, a, partials);
+    else
+        hipLaunchKernelGGL(k_marginal<double>, grid, dim3(NT), 0, st, (const Cx<double> *)state, sstride, a, partials);
+    hipLaunchKernelGGL(k_finish, dim3(uint32_t(nstates) << nqs), dim3(NT), 0, st, partials, nchunks, out);
+    return check(hipGetLastError());
+}
+
+uint32_t pauli_chunks(int n) {
+    uint64_t c = (uint64_t(1) << n) / 4096;
+    if (c < 1) c = 1;
+    if (c > 256) c = 256;
+    return uint32_t(c);
+}
+
+int launch_pauli(int dtype, const void *state, uint64_t sstride, uint32_t nstates, int n,
+                 const uint64_t *xmask, const uint64_t *zmask, int nterms, double *partials,
+                 double *out, hipStream_t st) {
+    if (nterms <= 0) return QSIM_OK;
+    const uint32_t nchunks = pauli_chunks(n);
+    const dim3 grid(nchunks, uint32_t(nterms), nstates);
+    if (dtype == QSIM_C64)
+        hipLaunchKernelGGL(k_pauli<float>, grid, dim3(NT), 0, st, (const Cx<float> *)state, sstride, n, xmask, zmask, partials);
+    else
+        hipLaunchKernelGGL(k_pauli<double>, grid, dim3(NT), 0, st, (const Cx<double> *)state, sstride, n, xmask, zmask, partials);
+    hipLaunchKernelGGL(k_finish, dim3(uint32_t(nstates) * uint32_t(nterms) * 2), dim3(NT), 0, st,
+                       partials, nchunks, out);
+    return check(hipGetLastError());
+}
+
+int launch_collapse(int dtype, void *state, int n, int q, int outcome, double scale, hipStream_t st) {
+    const uint64_t len = uint64_t(1) << n;
+    if (dtype == QSIM_C64)
+        hipLaunchKernelGGL(k_collapse<float>, dim3(grid_for(len)), dim3(NT), 0, st, (Cx<float> *)state, len, q, outcome, float(scale));
+    else
+        hipLaunchKernelGGL(k_collapse<double>, dim3(grid_for(len)), dim3(NT), 0, st, (Cx<double> *)state, len, q, outcome, scale);
+    return check(hipGetLastError());
+}
+
+}  // namespace qk

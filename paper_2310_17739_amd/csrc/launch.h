@@ -1,0 +1,85 @@
+// Host-callable launchers of the gfx950 kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "host.h"
+
+namespace qk {
+
+// Record a failed HIP call (error string and the call site) for
+// qsim_last_error; returns QSIM_OK for hipSuccess, else QSIM_E_HIP.
+int note_hip(hipError_t e, const char *where);
+
+// Tile of a pass: the qubits outside the tile enumerate the tiles
+// (blockIdx.x), the low c qubits are contiguous inside the tile, and hi[]
+// lists the other tile qubits in ascending order.
+struct TileArgs {
+    uint64_t rest_mask;   // qubits not in the tile
+    uint64_t tile_mask;   // qubits in the tile (j bit b <-> b-th lowest of them)
+    int32_t n, t, c, nhi;
+    uint8_t hi[48];
+};
+
+// Measurement inputs / outputs of a batched program (per state b, slot s:
+// index b * nslots + s).
+struct MeasArgs {
+    const double *uniforms;   // draws in [0,1)
+    const int32_t *forced;    // >= 0: force this outcome (may be null)
+    int32_t *outcomes;
+    double *probs;            // probability of the recorded outcome
+    int32_t *status;          // per state: 0, or a negative QSIM_E_* code
+    int32_t *fail_at;         // per state: instruction index of the failure
+    int32_t nslots;
+};
+
+enum : uint32_t { TF_INIT_ZERO = 1, TF_NO_STORE = 2 };
+
+// Enable > 64 KiB of dynamic LDS for the tile kernels.  Idempotent.
+int init_kernels();
+size_t max_lds_bytes();
+
+// LDS bytes of a tile pass: the tile, then the pass's operator records and
+// coefficients.
+size_t tile_lds_bytes(size_t elem, int t, uint32_t nops, uint32_t ncoefs);
+
+// One tiled pass (or a whole resident program when t == n) over `nstates`
+// states spaced `sstride` elements apart: operator records [ob, oe) whose
+// coefficients occupy [cb, ce) (elements of the state dtype); the
+// coefficients of state b are read at coefs + b * cstride.
+int launch_tile(int dtype, void *state, uint64_t sstride, uint32_t nstates, const TileArgs &ta,
+                const qs::DevOp *ops, uint32_t ob, uint32_t oe, const void *coefs, uint32_t cb,
+                uint32_t ce, uint64_t cstride, const MeasArgs *ma, uint32_t flags,
+                hipStream_t st);
+
+// One operator over the whole state (positions are global qubits).
+int launch_sweep(int dtype, void *state, uint64_t sstride, uint32_t nstates, int n,
+                 const qs::DevOp &op, const void *coefs, hipStream_t st);
+
+// |0...0> in every state of a batch.
+int launch_init_zero(int dtype, void *state, uint64_t sstride, uint32_t nstates, int n,
+                     hipStream_t st);
+
+// Marginal weights: for every bin j of the qubits qs[0..nqs-1] (j = sum_i
+// bit(qs[i]) 2^i), sum of |a_x|^2 over x with those bits; FP64, fixed order.
+// Writes partial sums to `partials` ([nstates][2^nqs][nchunks]) and the
+// final sums to `out` ([nstates][2^nqs]).
+int launch_marginal(int dtype, const void *state, uint64_t sstride, uint32_t nstates, int n,
+                    const int *qs, int nqs, double *partials, double *out, hipStream_t st);
+uint32_t marginal_chunks(int n, int nqs);
+
+// Pauli-term overlaps S_k = sum_x (-1)^{popcount(x & z_k)} conj(a[x ^ x_k]) a[x]
+// (complex, FP64) for terms on device (masks arrays), written as
+// out[(b * nterms + k) * 2 + {0,1}].
+int launch_pauli(int dtype, const void *state, uint64_t sstride, uint32_t nstates, int n,
+                 const uint64_t *xmask, const uint64_t *zmask, int nterms, double *partials,
+                 double *out, hipStream_t st);
+uint32_t pauli_chunks(int n);
+
+// Keep the half with bit q == outcome, scale it by `scale`, zero the other.
+int launch_collapse(int dtype, void *state, int n, int q, int outcome, double scale,
+                    hipStream_t st);
+
+}  // namespace qk

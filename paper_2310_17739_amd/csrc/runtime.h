@@ -1,0 +1,48 @@
+// Compiled circuits and their device tables (shared by the single-state
+// calls, the batched form and the server).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "host.h"
+#include "launch.h"
+
+namespace qs {
+
+struct PassInfo {
+    bool strided = false;
+    qk::TileArgs ta{};
+};
+
+struct Compiled {
+    PackedPlan plan;
+    std::vector<PassInfo> passes;
+    qsim_apply_stats stats{};
+};
+
+// Device copies of a packed plan with a pinned staging buffer.
+struct DeviceTables {
+    DevOp *d_ops = nullptr;
+    size_t cap_ops = 0;
+    void *d_coefs = nullptr;
+    size_t cap_coefs = 0;
+    void *h_stage = nullptr;
+    size_t cap_stage = 0;
+    hipEvent_t stage_ev = nullptr;
+    bool stage_ev_valid = false;
+};
+
+size_t elem_bytes(int dtype);
+int env_int(const char *name, int dflt);
+int resident_max(int dtype);
+void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc, PlanConfig *pc);
+int compile_circuit(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
+                    const double *params, const qsim_fuse_opts *opt, Compiled *out);
+int upload_plan(DeviceTables *dt, int dtype, const PackedPlan &plan, hipStream_t st);
+void free_tables(DeviceTables *dt);
+int enqueue_passes(const Compiled &c, const DeviceTables &dt, int dtype, void *state,
+                   hipStream_t st, bool init_zero_first);
+
+}  // namespace qs

@@ -1,0 +1,339 @@
+"""ctypes binding of the C ABI in ``include/qsim.h``.
+
+This module only marshals arguments: every step of the simulation runs in
+``libqsim.so`` (host compile in C++, sweeps and reductions in HIP kernels on
+the GPU).  PyTorch provides the device memory and the stream.  If the
+library has not been built, importing this module raises an error: there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from workloads import GATE_DTYPE, PAULI_DTYPE
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("QSIM_LIB") or os.path.join(_HERE, "libqsim.so")
+
+C64, C128 = 1, 2
+OK, E_ARG, E_QUBIT, E_NOMEM, E_ZERO_PROB, E_NOT_DEFINITE, E_HIP, E_CAPACITY, E_UNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+F_ONE_OP_PER_PASS, F_NO_SPARSE = 1, 2
+
+
+class QsimError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        msg = _lib.qsim_strerror(code).decode() if _lib is not None else str(code)
+        if code == E_HIP and _lib is not None:
+            msg += " [" + _lib.qsim_last_error().decode() + "]"
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+        self.code = code
+
+
+class qsim_fuse_opts(C.Structure):
+    _fields_ = [("level", C.c_int32), ("max_width", C.c_int32), ("tile_qubits", C.c_int32),
+                ("flags", C.c_int32)]
+
+
+class qsim_apply_stats(C.Structure):
+    _fields_ = [("input_gates", C.c_int64), ("ops_after", C.c_int64 * 6), ("fused_ops", C.c_int64),
+                ("passes", C.c_int64), ("terms", C.c_int64), ("bytes_moved", C.c_int64),
+                ("compile_seconds", C.c_double), ("tile_qubits", C.c_int32), ("max_width", C.c_int32)]
+
+    def as_dict(self):
+        return {"input_gates": self.input_gates, "ops_after": list(self.ops_after),
+                "fused_ops": self.fused_ops, "passes": self.passes, "terms": self.terms,
+                "bytes_moved": self.bytes_moved, "compile_seconds": self.compile_seconds,
+                "tile_qubits": self.tile_qubits, "max_width": self.max_width}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = C.CDLL(LIB_PATH)
+    P, I, SZ, D = C.c_void_p, C.c_int, C.c_size_t, C.c_double
+    sig = {
+        "qsim_version": ([], I),
+        "qsim_strerror": ([I], C.c_char_p),
+        "qsim_last_error": ([], C.c_char_p),
+        "qsim_create": ([I, I, P, SZ, P, P], I),
+        "qsim_destroy": ([P], I),
+        "qsim_set_stream": ([P, P], I),
+        "qsim_init_zero": ([P], I),
+        "qsim_apply": ([P, P, SZ, P, P, P], I),
+        "qsim_last_stats": ([P, P], I),
+        "qsim_measure": ([P, I, D, P, P], I),
+        "qsim_measure_assert": ([P, I, P], I),
+        "qsim_reset": ([P, I], I),
+        "qsim_expval": ([P, P, SZ, P], I),
+        "qsim_probs": ([P, P, I, P], I),
+        "qsim_norm": ([P, P], I),
+        "qsim_get_state": ([P, P], I),
+        "qsim_set_state": ([P, P], I),
+        "qsim_debug_fuse": ([I, P, SZ, P, P, P, P, P, P, SZ, SZ, P, P], I),
+        "qsim_compile": ([I, I, P, SZ, P, P, P, P], I),
+        "qsim_run": ([P, P], I),
+        "qsim_program_graph": ([P, P, I], I),
+        "qsim_run_timed": ([P, P], I),
+        "qsim_program_kernel_ms": ([P, P, P], I),
+        "qsim_program_stats": ([P, P], I),
+        "qsim_program_destroy": ([P], I),
+        "qsim_debug_plan": ([I, I, P, SZ, P, P, P, P], I),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _bind_optional(lib)
+    return lib
+
+
+def _bind_optional(lib):
+    """Entry points of the batched and served forms (declared in qsim.h)."""
+    P, I, SZ, D = C.c_void_p, C.c_int, C.c_size_t, C.c_double
+    opt = {
+        "qsim_batch_create": ([P, I, P, P], I),
+        "qsim_batch_run": ([P, P], I),
+        "qsim_batch_results": ([P, P, P, P, P, P, P], I),
+        "qsim_batch_destroy": ([P], I),
+        "qsim_batch_info": ([P, P], I),
+        "qsim_server_create": ([P, P], I),
+        "qsim_server_submit": ([P, P, P], I),
+        "qsim_server_poll": ([P, P, I, P], I),
+        "qsim_server_stats": ([P, P], I),
+        "qsim_server_destroy": ([P], I),
+        "qsim_server_get_state": ([P, C.c_int64, P], I),
+    }
+    for name, (args, res) in opt.items():
+        if hasattr(lib, name):
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = res
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def check(rc: int, what: str = ""):
+    if rc != OK:
+        raise QsimError(rc, what)
+
+
+def _p(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def _opts(level=None, max_width=None, tile_qubits=None, flags=0):
+    if level is None and max_width is None and tile_qubits is None and not flags:
+        return None
+    o = qsim_fuse_opts()
+    o.level = 5 if level is None else int(level)
+    o.max_width = int(max_width or 0)
+    o.tile_qubits = int(tile_qubits or 0)
+    o.flags = int(flags)
+    return o
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class StateVector:
+    """A 2^n complex state in device memory owned by a torch tensor."""
+
+    def __init__(self, n: int, dtype: str = "complex128", device="cuda", stream=None, tensor=None):
+        torch = _torch()
+        self.n = int(n)
+        self.dtype = QSIM_DTYPES[dtype]
+        tdt = torch.complex64 if self.dtype == C64 else torch.complex128
+        if tensor is None:
+            tensor = torch.empty(1 << self.n, dtype=tdt, device=device)
+        assert tensor.dtype == tdt and tensor.is_contiguous() and tensor.numel() >= (1 << self.n)
+        self.tensor = tensor
+        self.stream = stream if stream is not None else torch.cuda.current_stream(tensor.device)
+        h = C.c_void_p()
+        check(_lib.qsim_create(self.n, self.dtype, C.c_void_p(tensor.data_ptr()),
+                               tensor.numel() * tensor.element_size(),
+                               C.c_void_p(self.stream.cuda_stream), C.byref(h)), "qsim_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.qsim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------------- calls
+    def qsim_init_zero(self):
+        check(_lib.qsim_init_zero(self.h), "qsim_init_zero")
+
+    def qsim_apply(self, gates, mats=None, params=None, level=None, max_width=None,
+                   tile_qubits=None, flags=0):
+        g = np.ascontiguousarray(gates, dtype=GATE_DTYPE)
+        m = None if mats is None else np.ascontiguousarray(mats, dtype=np.complex128)
+        pr = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+        o = _opts(level, max_width, tile_qubits, flags)
+        check(_lib.qsim_apply(self.h, _p(g), len(g), _p(m), _p(pr), C.byref(o) if o else None),
+              "qsim_apply")
+
+    def qsim_last_stats(self) -> dict:
+        s = qsim_apply_stats()
+        check(_lib.qsim_last_stats(self.h, C.byref(s)))
+        return s.as_dict()
+
+    def qsim_measure(self, q: int, u: float):
+        o, p = C.c_int(), C.c_double()
+        check(_lib.qsim_measure(self.h, int(q), float(u), C.byref(o), C.byref(p)), "qsim_measure")
+        return o.value, p.value
+
+    def qsim_measure_assert(self, q: int) -> float:
+        p = C.c_double()
+        check(_lib.qsim_measure_assert(self.h, int(q), C.byref(p)), "qsim_measure_assert")
+        return p.value
+
+    def qsim_reset(self, q: int):
+        check(_lib.qsim_reset(self.h, int(q)), "qsim_reset")
+
+    def qsim_expval(self, terms) -> float:
+        t = np.ascontiguousarray(terms, dtype=PAULI_DTYPE)
+        out = C.c_double()
+        check(_lib.qsim_expval(self.h, _p(t), len(t), C.byref(out)), "qsim_expval")
+        return out.value
+
+    def qsim_probs(self, qs) -> np.ndarray:
+        q = np.ascontiguousarray(qs, dtype=np.int32)
+        out = np.zeros(1 << len(q), dtype=np.float64)
+        check(_lib.qsim_probs(self.h, _p(q), len(q), _p(out)), "qsim_probs")
+        return out
+
+    def qsim_norm(self) -> float:
+        out = C.c_double()
+        check(_lib.qsim_norm(self.h, C.byref(out)), "qsim_norm")
+        return out.value
+
+    def qsim_get_state(self) -> np.ndarray:
+        out = np.empty(1 << self.n, dtype=np.complex64 if self.dtype == C64 else np.complex128)
+        check(_lib.qsim_get_state(self.h, _p(out)), "qsim_get_state")
+        return out
+
+    def qsim_set_state(self, psi):
+        src = np.ascontiguousarray(psi, dtype=np.complex64 if self.dtype == C64 else np.complex128)
+        assert src.shape == (1 << self.n,)
+        check(_lib.qsim_set_state(self.h, _p(src)), "qsim_set_state")
+
+
+class Program:
+    """A circuit compiled once (qsim_compile) and replayed with qsim_run."""
+
+    def __init__(self, n, gates, dtype="complex128", mats=None, params=None, level=None,
+                 max_width=None, tile_qubits=None, flags=0):
+        g = np.ascontiguousarray(gates, dtype=GATE_DTYPE)
+        m = None if mats is None else np.ascontiguousarray(mats, dtype=np.complex128)
+        pr = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+        o = _opts(level, max_width, tile_qubits, flags)
+        self.n = int(n)
+        self.dtype = QSIM_DTYPES[dtype]
+        p = C.c_void_p()
+        check(_lib.qsim_compile(self.n, self.dtype, _p(g), len(g), _p(m), _p(pr),
+                                C.byref(o) if o else None, C.byref(p)), "qsim_compile")
+        self.p = p
+
+    def qsim_run(self, sv: "StateVector"):
+        check(_lib.qsim_run(sv.h, self.p), "qsim_run")
+
+    def qsim_run_timed(self, sv: "StateVector"):
+        check(_lib.qsim_run_timed(sv.h, self.p), "qsim_run_timed")
+
+    def qsim_program_kernel_ms(self):
+        ms, n = C.c_double(), C.c_int64()
+        check(_lib.qsim_program_kernel_ms(self.p, C.byref(ms), C.byref(n)), "qsim_program_kernel_ms")
+        return ms.value, n.value
+
+    def qsim_program_graph(self, sv: "StateVector", enable=True):
+        check(_lib.qsim_program_graph(self.p, sv.h, int(bool(enable))), "qsim_program_graph")
+
+    def qsim_program_stats(self) -> dict:
+        s = qsim_apply_stats()
+        check(_lib.qsim_program_stats(self.p, C.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "p", None):
+            _lib.qsim_program_destroy(self.p)
+            self.p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+QSIM_DTYPES = {"complex64": C64, "c64": C64, "complex128": C128, "c128": C128}
+
+
+def qsim_debug_fuse(n, gates, mats=None, params=None, level=5, max_width=4, flags=0):
+    """Host-only: the fused operators as a list of (qubits, matrix), and the
+    operator count after each fusion level."""
+    g = np.ascontiguousarray(gates, dtype=GATE_DTYPE)
+    m = None if mats is None else np.ascontiguousarray(mats, dtype=np.complex128)
+    pr = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+    o = _opts(level, max_width, None, flags)
+    cap = max(len(g), 1)
+    out_k = np.zeros(cap, dtype=np.int32)
+    out_q = np.zeros(5 * cap, dtype=np.int32)
+    cap_d = 2 * 1024 * cap
+    out_m = np.zeros(min(cap_d, 2 * 1024 * 4096 + 2 * 16 * cap), dtype=np.float64)
+    nops = C.c_size_t()
+    counts = np.zeros(6, dtype=np.int64)
+    rc = _lib.qsim_debug_fuse(int(n), _p(g), len(g), _p(m), _p(pr), C.byref(o) if o else None,
+                              _p(out_k), _p(out_q), _p(out_m), cap, len(out_m), C.byref(nops), _p(counts))
+    if rc == E_CAPACITY:
+        out_m = np.zeros(2 * 1024 * cap, dtype=np.float64)
+        rc = _lib.qsim_debug_fuse(int(n), _p(g), len(g), _p(m), _p(pr), C.byref(o) if o else None,
+                                  _p(out_k), _p(out_q), _p(out_m), cap, len(out_m), C.byref(nops), _p(counts))
+    check(rc, "qsim_debug_fuse")
+    ops = []
+    pos = 0
+    for i in range(nops.value):
+        k = int(out_k[i])
+        d = 1 << k
+        mat = (out_m[pos:pos + 2 * d * d:2] + 1j * out_m[pos + 1:pos + 2 * d * d:2]).reshape(d, d)
+        pos += 2 * d * d
+        ops.append((list(out_q[5 * i:5 * i + k]), mat))
+    return ops, counts
+
+
+def qsim_debug_plan(n, gates, dtype="complex128", mats=None, params=None, level=None,
+                    max_width=None, tile_qubits=None, flags=0) -> dict:
+    """Host-only: compile statistics (fused operators, passes) without a GPU."""
+    g = np.ascontiguousarray(gates, dtype=GATE_DTYPE)
+    m = None if mats is None else np.ascontiguousarray(mats, dtype=np.complex128)
+    pr = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+    o = _opts(level, max_width, tile_qubits, flags)
+    s = qsim_apply_stats()
+    check(_lib.qsim_debug_plan(int(n), QSIM_DTYPES[dtype], _p(g), len(g), _p(m), _p(pr),
+                               C.byref(o) if o else None, C.byref(s)), "qsim_debug_plan")
+    return s.as_dict()
+
+
+def exported_symbols():
+    """Names of every function declared in include/qsim.h."""
+    import re
+    hdr = os.path.join(os.path.dirname(_HERE), "include", "qsim.h")
+    txt = open(hdr).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(qsim_[a-z0-9_]+)\s*\(", txt)))

@@ -1,0 +1,165 @@
+"""Host-only checks of the library's lowering and fusion (no GPU needed).
+
+The fused operators exported by qsim_debug_fuse are applied by the CPU
+oracle as dense matrix records; the result must equal the unfused circuit
+run by the oracle (fusion is exact matrix algebra, Section 3.2: the update
+need not be unitary, which is what makes fusion possible).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from paper_2310_17739_amd import qsim
+
+
+def fused_as_records(ops):
+    recs, mats, off = [], [], 0
+    for qs, m in ops:
+        recs.append((W.KIND_MAT, qs, ()))
+        mats.append(m.ravel())
+        off += m.size
+    g = W.gates(recs)
+    o = 0
+    for i, (qs, m) in enumerate(ops):
+        g[i]["mat_off"] = o
+        o += m.size
+    return g, (np.concatenate(mats) if mats else np.zeros(0, complex))
+
+
+def check_fused_equals_unfused(n, g, level, width, tol=1e-12, params=None, mats=None):
+    ops, counts = qsim.qsim_debug_fuse(n, g, mats=mats, params=params, level=level, max_width=width)
+    fg, fm = fused_as_records(ops)
+    psi0 = W.random_state(n, seed=level * 10 + width)
+    want, _, _ = oracle.run(n, g, psi=psi0, mats=mats, params=params)
+    got, _, _ = oracle.run(n, fg, psi=psi0, mats=fm)
+    assert oracle.infidelity(want, got) < tol
+    np.testing.assert_allclose(got, want, atol=1e-11)
+    return ops, counts
+
+
+@pytest.mark.parametrize("level", [0, 1, 2, 3, 4, 5])
+def test_random_circuit_fusion_levels(level):
+    n = 6
+    g = W.random_circuit(n, 200, seed=1)
+    ops, counts = check_fused_equals_unfused(n, g, level, 4)
+    c = [x for x in counts if x >= 0]
+    assert all(a >= b for a, b in zip(c, c[1:]))
+    assert len(ops) == c[-1]
+
+
+@pytest.mark.parametrize("width", [2, 3, 4, 5])
+def test_all_gate_kinds_fusion(width):
+    n = 7
+    g = W.random_all_kinds(n, 150, seed=width)
+    check_fused_equals_unfused(n, g, 5, width)
+
+
+def test_pauli_exponentials_fusion():
+    n = 8
+    g, _, _ = W.pauli_exponential_circuit(n, 120, seed=5)
+    ops, counts = check_fused_equals_unfused(n, g, 5, 4)
+    # the F1..F2 steps merge each exponential's ladder into about 3 C2 operators
+    assert counts[4] < counts[0] / 2.0
+    # width-4 fusion leaves at most about one operator per exponential
+    assert counts[5] <= 120
+
+
+def test_matrix_records_and_both_orders():
+    n = 6
+    rng = np.random.default_rng(3)
+    recs, mats, off = [], [], 0
+    for i in range(30):
+        k = int(rng.integers(1, 4))
+        qs = list(rng.choice(n, size=k, replace=False))
+        m = W.random_complex_matrix(1 << k, seed=i)
+        recs.append((W.KIND_MAT, qs, ()))
+        mats.append(m.ravel())
+    g = W.gates(recs)
+    o = 0
+    for i in range(len(g)):
+        g[i]["mat_off"] = o
+        o += len(mats[i])
+    allm = np.concatenate(mats)
+    for level in (2, 4, 5):
+        ops, _ = qsim.qsim_debug_fuse(n, g, mats=allm, level=level, max_width=4)
+        fg, fm = fused_as_records(ops)
+        psi0 = W.random_state(n, 1)
+        want, _, _ = oracle.run(n, g, psi=psi0, mats=allm)
+        got, _, _ = oracle.run(n, fg, psi=psi0, mats=fm)
+        # non-unitary random factors: compare relative to the result's size
+        assert np.max(np.abs(got - want)) < 1e-10 * np.max(np.abs(want))
+
+
+def test_parameter_slots_bind_angles():
+    n = 5
+    recs = []
+    for e in range(6):
+        W.compile_pauli_exponential(np.array([e % n, (e + 2) % n]), np.array([1, 2]), 0.0, e, recs)
+    g = W.gates(recs)
+    params = np.linspace(-0.7, 0.9, 6)
+    check_fused_equals_unfused(n, g, 5, 4, params=params)
+
+
+def test_barrier_fences_fusion():
+    g = W.gates([(W.KIND_H, (0,), ()), (W.KIND_BARRIER, (0,), ()), (W.KIND_H, (0,), ())])
+    ops, counts = qsim.qsim_debug_fuse(2, g, level=5, max_width=4)
+    assert len(ops) == 2
+    g2 = W.gates([(W.KIND_H, (0,), ()), (W.KIND_H, (0,), ())])
+    ops2, _ = qsim.qsim_debug_fuse(2, g2, level=5, max_width=4)
+    assert len(ops2) == 1
+    np.testing.assert_allclose(ops2[0][1], np.eye(2), atol=1e-15)
+
+
+def test_f2_needs_swap_normalisation_for_reversed_pairs():
+    """Level 3 (F2 without SWAP normalisation) cannot merge CX(a,b) with
+    CX(b,a); level 4 (the paper's normalisation, Section 4.2) can."""
+    g = W.gates([(W.KIND_CX, (0, 1), ()), (W.KIND_CX, (1, 0), ()), (W.KIND_CX, (0, 1), ())])
+    _, c3 = qsim.qsim_debug_fuse(2, g, level=3, max_width=4)
+    _, c4 = qsim.qsim_debug_fuse(2, g, level=4, max_width=4)
+    assert c3[3] == 3 and c4[4] == 1
+    check_fused_equals_unfused(2, g, 3, 4)
+    check_fused_equals_unfused(2, g, 4, 4)
+
+
+def test_lowering_errors():
+    bad_q = W.gates([(W.KIND_H, (7,), ())])
+    with pytest.raises(qsim.QsimError) as e:
+        qsim.qsim_debug_fuse(3, bad_q)
+    assert e.value.code == qsim.E_QUBIT
+    dup = W.gates([(W.KIND_CX, (1, 1), ())])
+    with pytest.raises(qsim.QsimError) as e:
+        qsim.qsim_debug_fuse(3, dup)
+    assert e.value.code == qsim.E_QUBIT
+    nan = W.gates([(W.KIND_RX, (0,), (float("nan"),))])
+    with pytest.raises(qsim.QsimError) as e:
+        qsim.qsim_debug_fuse(3, nan)
+    assert e.value.code == qsim.E_ARG
+    meas = W.gates([(W.KIND_MEASURE, (0,), (), 0)])
+    with pytest.raises(qsim.QsimError) as e:
+        qsim.qsim_debug_fuse(3, meas)
+    assert e.value.code == qsim.E_UNSUPPORTED
+
+
+def test_plan_statistics():
+    """The pass planner packs several fused operators per full-state pass."""
+    g, _, _ = W.pauli_exponential_circuit(21, 1000, seed=2)
+    s = qsim.qsim_debug_plan(21, g, "complex128")
+    assert s["input_gates"] == len(g)
+    assert s["passes"] < s["fused_ops"]
+    one = qsim.qsim_debug_plan(21, g, "complex128", flags=qsim.F_ONE_OP_PER_PASS)
+    assert one["passes"] == one["fused_ops"]
+    # a state that fits one workgroup's LDS runs as resident passes over the
+    # whole state, split only where the operator tables outgrow the LDS
+    g14, _, _ = W.pauli_exponential_circuit(14, 300, seed=2)
+    s14 = qsim.qsim_debug_plan(14, g14, "complex64")
+    assert s14["tile_qubits"] == 14 and 1 <= s14["passes"] <= s14["fused_ops"] / 10
+    g14s, _, _ = W.pauli_exponential_circuit(14, 20, seed=2)
+    assert qsim.qsim_debug_plan(14, g14s, "complex64")["passes"] == 1
+
+
+def test_abi_exports_every_declared_symbol():
+    import ctypes
+    lib = ctypes.CDLL(qsim.LIB_PATH)
+    missing = [s for s in qsim.exported_symbols() if not hasattr(lib, s)]
+    assert not missing, missing

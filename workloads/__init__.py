@@ -111,6 +111,7 @@ def random_circuit(n: int = 6, n_gates: int = 200, seed: int = 1) -> np.ndarray:
     rng = _rng(seed)
     kinds = [KIND_H, KIND_X, KIND_RY, KIND_RZ, KIND_CX]
     out = np.zeros(n_gates, dtype=GATE_DTYPE)
+    out["slot"] = -1
     for i in range(n_gates):
         k = kinds[rng.integers(len(kinds))]
         out[i]["kind"] = k
@@ -135,6 +136,7 @@ def random_all_kinds(n: int, n_gates: int, seed: int,
              if a <= min(n, max_arity) and k not in (KIND_MEASURE, KIND_RESET,
                                                      KIND_ASSERT0)]
     out = np.zeros(n_gates, dtype=GATE_DTYPE)
+    out["slot"] = -1
     for i in range(n_gates):
         k = kinds[rng.integers(len(kinds))]
         a = KIND_QUBITS[k]
@@ -330,3 +332,21 @@ def random_state(n: int, seed: int) -> np.ndarray:
     rng = _rng(seed, 98)
     v = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
     return v / np.linalg.norm(v)
+
+
+def inverse_circuit(g: np.ndarray) -> np.ndarray:
+    """The gate list of the inverse of a circuit made of self-inverse gates
+    (H, X, Y, Z, CX, CY, CZ, SWAP) and rotations (angle negated): records in
+    reverse order."""
+    self_inverse = {KIND_ID, KIND_H, KIND_X, KIND_Y, KIND_Z, KIND_CX, KIND_CY,
+                    KIND_CZ, KIND_SWAP, KIND_CCX, KIND_CSWAP, KIND_C3X, KIND_C4X}
+    rot = {KIND_RX, KIND_RY, KIND_RZ, KIND_U1, KIND_CRX, KIND_CRY, KIND_CRZ,
+           KIND_CU1, KIND_RXX, KIND_RZZ}
+    out = g[::-1].copy()
+    for i in range(len(out)):
+        k = int(out[i]["kind"])
+        if k in rot:
+            out[i]["theta"][0] = -out[i]["theta"][0]
+        elif k not in self_inverse:
+            raise ValueError(f"no inverse record for kind {k}")
+    return out
