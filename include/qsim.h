@@ -209,6 +209,74 @@ int qsim_program_kernel_ms(qsim_prog p, double *ms, int64_t *launches);
 int qsim_program_stats(qsim_prog p, qsim_apply_stats *out);
 int qsim_program_destroy(qsim_prog p);
 
+/* -------------------------------------------------- batched programs */
+
+/* Many states run the same program in one device-side schedule: the
+ * trajectories of a circuit with mid-circuit measurements (Section 4.3:
+ * without measurement assertion every shot is its own run), or many
+ * parameter sets of one circuit template.  A group is a set of states of
+ * one width sharing a program; a batch holds several groups.  Programs may
+ * contain MEASURE, ASSERT0 and RESET records: the decision is taken on the
+ * device from the group's uniform draws, so no host round trip is needed.
+ * All results are accumulated in FP64 and read back by qsim_batch_results. */
+typedef struct qsim_batch *qsim_batch_h;
+
+typedef struct qsim_batch_group {
+    int32_t n;               /* state width (qubits) */
+    int32_t n_states;        /* states in the group (<= 65535) */
+    const qsim_gate *g;      /* the shared program */
+    size_t ng;
+    const double *mats;      /* MAT pool (complex128), or NULL */
+    const double *params;    /* n_states x n_params angles read by records with
+                                slot >= 0 (RX, RY, RZ, RXX, RZZ), or NULL */
+    int32_t n_params;
+    const double *uniforms;  /* n_states x n_slots draws in [0,1), or NULL */
+    const int32_t *forced;   /* n_states x n_slots outcomes to force (-1: draw), or NULL */
+    int32_t n_slots;         /* measurement slots per state */
+    const qsim_pauli *terms; /* observable evaluated at the end, or NULL */
+    size_t n_terms;
+    void *dev_states;        /* caller-owned device buffer of n_states * 2^n
+                                elements (state b at offset b * 2^n), or NULL
+                                to let the batch allocate it */
+} qsim_batch_group;
+
+typedef struct qsim_batch_opts {
+    int32_t dtype;           /* QSIM_C64 or QSIM_C128 */
+    int32_t use_graph;       /* 1: record the whole run once as a HIP graph and replay it */
+    int32_t max_params;      /* angle slots per fused operator (0 = 2) */
+    int32_t pad;
+    qsim_fuse_opts fuse;     /* level 0 selects the default (5) */
+} qsim_batch_opts;
+
+typedef struct qsim_batch_info {
+    int64_t states;
+    int64_t input_gates;     /* summed over groups, per state */
+    int64_t fused_ops;
+    int64_t passes;          /* summed over groups */
+    int64_t state_bytes;
+    int64_t coef_bytes;
+    double compile_seconds;
+} qsim_batch_info;
+
+/* Compile every group once (lowering, fusion, plan; angle-dependent
+ * operators keep their cos/sin basis blocks) and allocate device memory.
+ * Errors as qsim_compile, plus QSIM_E_CAPACITY (n_states > 65535). */
+int qsim_batch_create(const qsim_batch_group *groups, int n_groups, const qsim_batch_opts *opt,
+                      qsim_batch_h *out);
+/* Run every group from |0...0> (asynchronous on hip_stream): bind angles,
+ * apply the program, decide measurements on the device, reduce norms and
+ * Pauli overlaps. */
+int qsim_batch_run(qsim_batch_h b, void *hip_stream);
+/* Synchronise and read one group's results (NULL to skip an output):
+ * outcomes / probs: n_states x n_slots (outcome, probability of it);
+ * expvals: <H>/<psi|psi> per state; norms: <psi|psi> per state;
+ * status: 0, or the QSIM_E_* code of a failed assertion / reset. */
+int qsim_batch_results(qsim_batch_h b, int group, int32_t *outcomes, double *probs,
+                       double *expvals, double *norms, int32_t *status);
+int qsim_batch_get_state(qsim_batch_h b, int group, int index, void *host_dst);
+int qsim_batch_info_get(qsim_batch_h b, qsim_batch_info *out);
+int qsim_batch_destroy(qsim_batch_h b);
+
 /* ------------------------------------------------------- host-only tools */
 
 /* Run lowering and fusion only (no device): writes the fused operators as

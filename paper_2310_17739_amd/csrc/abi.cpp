@@ -87,6 +87,10 @@ int validate_plan(int n, int dtype, const Compiled &c) {
     for (size_t i = 0; i < c.passes.size(); i++) {
         const PassInfo &pi = c.passes[i];
         int width = n;
+        if (pi.kind == Pass::MEASURE) {
+            if (p.pass_begin[i] != p.pass_begin[i + 1] || pi.meas.q < 0 || pi.meas.q >= n) return QSIM_E_ARG;
+            continue;
+        }
         if (!pi.strided) {
             const qk::TileArgs &ta = pi.ta;
             if (ta.n != n || ta.t < 1 || ta.t > n || ta.t > resident_max(dtype) || ta.c < 0 ||
@@ -110,7 +114,12 @@ int validate_plan(int n, int dtype, const Compiled &c) {
             return QSIM_E_ARG;
         for (uint32_t j = p.pass_begin[i]; j < p.pass_begin[i + 1]; j++) {
             const DevOp &o = p.ops[j];
-            if (o.kind != DEVOP_MAT || o.k < 1 || o.k > kMaxK || o.k > width) return QSIM_E_ARG;
+            if (o.kind != DEVOP_MAT) {
+                // measurement records run only inside resident (whole-state) passes
+                if (pi.strided || pi.ta.t != n || o.pos[0] >= n || o.kind > DEVOP_RESET) return QSIM_E_ARG;
+                continue;
+            }
+            if (o.k < 1 || o.k > kMaxK || o.k > width) return QSIM_E_ARG;
             if (!pi.strided && dtype == QSIM_C128 && o.k > 4) return QSIM_E_ARG;
             for (int a = 0; a < o.k; a++) {
                 if (o.pos[a] >= width) return QSIM_E_ARG;
@@ -119,9 +128,11 @@ int validate_plan(int n, int dtype, const Compiled &c) {
             const uint32_t d = 1u << o.k;
             const uint32_t mask = (d >= 32) ? 0xffffffffu : ((1u << d) - 1);
             if (!o.present || (o.present & ~mask)) return QSIM_E_ARG;
-            const size_t need = size_t(o.coef) + size_t(__builtin_popcount(o.present)) * d;
+            const size_t need = size_t(o.coef) + size_t(__builtin_popcount(o.present)) * d *
+                                                     (size_t(1) << p.op_np[j]);
             if (need > p.coefs.size()) return QSIM_E_ARG;
             if (!pi.strided && (o.coef < p.coef_begin[i] || need > p.coef_begin[i + 1])) return QSIM_E_ARG;
+            if (p.op_np[j] < 0 || p.op_np[j] > 3) return QSIM_E_ARG;
         }
     }
     return QSIM_OK;
@@ -129,28 +140,38 @@ int validate_plan(int n, int dtype, const Compiled &c) {
 
 int compile_circuit(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
                     const double *params, const qsim_fuse_opts *opt, Compiled *out) {
+    return compile_program(n, dtype, g, ng, mats, params, false, false, 0, opt, out);
+}
+
+int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
+                    const double *params, bool keep_params, bool allow_meas, int max_params,
+                    const qsim_fuse_opts *opt, Compiled *out) {
     double t0 = now_seconds();
     FuseConfig fc;
     PlanConfig pc;
     default_configs(n, dtype, opt, &fc, &pc);
+    fc.max_params = keep_params ? std::max(1, std::min(max_params, 3)) : 0;
     Lowered L;
-    int rc = lower(n, g, ng, mats, params, false, &L);
+    int rc = lower(n, g, ng, mats, params, keep_params, allow_meas, &L);
     if (rc) return rc;
     int64_t counts[6];
     fuse(n, &L, fc, counts);
     std::vector<uint32_t> present(L.ops.size()), meta(L.ops.size());
     for (size_t i = 0; i < L.ops.size(); i++) {
         present[i] = op_present(L.ops[i], fc.sparse);
+        // LDS holds the bound (per-state) coefficients: no cos/sin blocks
         meta[i] = uint32_t(sizeof(DevOp) + size_t(__builtin_popcount(present[i])) *
-                                               L.ops[i].dim() * (1u << L.ops[i].np) * elem_bytes(dtype));
+                                               L.ops[i].dim() * elem_bytes(dtype));
     }
     std::vector<Pass> passes;
-    plan_passes(n, L.ops, L.fence_after, meta, pc, &passes);
+    plan_passes(n, L, meta, pc, &passes);
     pack_plan(L.ops, present, passes, &out->plan);
     out->passes.clear();
     out->passes.reserve(passes.size());
     for (const Pass &p : passes) {
         PassInfo pi;
+        pi.kind = p.kind;
+        pi.meas = p.meas;
         pi.strided = p.strided;
         pi.ta.n = n;
         pi.ta.t = p.t;
@@ -173,7 +194,9 @@ int compile_circuit(int n, int dtype, const qsim_gate *g, size_t ng, const doubl
     s.tile_qubits = pc.one_op_per_pass ? 0 : pc.tile_qubits;
     s.max_width = fc.max_width;
     s.compile_seconds = now_seconds() - t0;
-    return validate_plan(n, dtype, *out);
+    // parameterised templates are validated after their coefficient layout
+    // is bound (qsim_batch_create)
+    return keep_params ? QSIM_OK : validate_plan(n, dtype, *out);
 }
 
 }  // namespace qs
@@ -272,6 +295,7 @@ int enqueue_passes(const Compiled &c, const DeviceTables &dt, int dtype, void *s
         const PassInfo &pi = c.passes[i];
         const uint32_t ob = p.pass_begin[i], oe = p.pass_begin[i + 1];
         int rc;
+        if (pi.kind == Pass::MEASURE) return QSIM_E_UNSUPPORTED;
         if (pi.strided) {
             for (uint32_t j = ob; j < oe; j++) {
                 rc = qk::launch_sweep(dtype, state, 0, 1, pi.ta.n, p.ops[j], dt.d_coefs, st);
@@ -727,7 +751,7 @@ int qsim_debug_fuse(int n, const qsim_gate *g, size_t ng, const double *mats, co
     int rc;
     int64_t cnt[6];
     try {
-        rc = lower(n, g, ng, mats, params, false, &L);
+        rc = lower(n, g, ng, mats, params, false, false, &L);
         if (rc) return rc;
         fuse(n, &L, fc, cnt);
     } catch (const std::bad_alloc &) {

@@ -180,43 +180,23 @@ int union_qubits(const Op &a, const Op &b, int *uq) {
     return n;
 }
 
-// epoch[i]: number of fences before op i
-std::vector<int> epochs(const Lowered &L) {
-    std::vector<int> ep(L.ops.size(), 0);
-    size_t f = 0;
-    std::vector<int> fa = L.fence_after;
-    std::sort(fa.begin(), fa.end());
-    int e = 0;
-    for (size_t i = 0; i < L.ops.size(); i++) {
-        while (f < fa.size() && fa[f] < int(i)) { e++; f++; }
-        ep[i] = e;
-    }
-    return ep;
-}
-
-void compact(Lowered *L, std::vector<int> *ep) {
+void compact(Lowered *L) {
     std::vector<Op> ops;
     std::vector<int> nep;
     ops.reserve(L->ops.size());
-    std::vector<int> newidx(L->ops.size(), -1);
+    nep.reserve(L->ops.size());
     for (size_t i = 0; i < L->ops.size(); i++) {
         if (L->ops[i].dead) continue;
-        newidx[i] = int(ops.size());
-        nep.push_back((*ep)[i]);
+        nep.push_back(L->op_epoch[i]);
         ops.push_back(std::move(L->ops[i]));
     }
-    // fences: after the last surviving op of each epoch boundary
-    std::vector<int> fences;
-    for (size_t i = 1; i < nep.size(); i++)
-        if (nep[i] != nep[i - 1]) fences.push_back(int(i) - 1);
-    if (!nep.empty() && nep[0] > 0) fences.insert(fences.begin(), -1);
     L->ops.swap(ops);
-    L->fence_after.swap(fences);
-    ep->swap(nep);
+    L->op_epoch.swap(nep);
 }
 
 // F1: merge wire-consecutive 1-qubit operators.
-void fuse_f1(int n, Lowered *L, std::vector<int> *ep, const FuseConfig &cfg) {
+void fuse_f1(int n, Lowered *L, const FuseConfig &cfg) {
+    const std::vector<int> *ep = &L->op_epoch;
     std::vector<int> last(n, -1);
     for (size_t i = 0; i < L->ops.size(); i++) {
         Op &o = L->ops[i];
@@ -231,11 +211,12 @@ void fuse_f1(int n, Lowered *L, std::vector<int> *ep, const FuseConfig &cfg) {
         }
         for (int t = 0; t < o.k; t++) last[o.q[t]] = int(i);
     }
-    compact(L, ep);
+    compact(L);
 }
 
 // F3: 2-qubit operators absorb the adjacent 1-qubit operator of each wire.
-void fuse_f3(int n, Lowered *L, std::vector<int> *ep, const FuseConfig &cfg) {
+void fuse_f3(int n, Lowered *L, const FuseConfig &cfg) {
+    const std::vector<int> *ep = &L->op_epoch;
     const size_t N = L->ops.size();
     // previous / next operator on the wire of each 1-qubit operator
     std::vector<int> prev(N, -1), next(N, -1), last(n, -1);
@@ -262,14 +243,15 @@ void fuse_f3(int n, Lowered *L, std::vector<int> *ep, const FuseConfig &cfg) {
             u.dead = true;
         }
     }
-    compact(L, ep);
+    compact(L);
 }
 
 // F2: merge wire-consecutive 2-qubit operators on the same pair.  Without
 // normalisation (`ordered`), only operators whose gates named the pair in the
 // same order merge.
-void fuse_f2(int n, Lowered *L, std::vector<int> *ep, const FuseConfig &cfg, bool ordered,
+void fuse_f2(int n, Lowered *L, const FuseConfig &cfg, bool ordered,
              const std::vector<int> &orient) {
+    const std::vector<int> *ep = &L->op_epoch;
     std::vector<int> last(n, -1);
     for (size_t i = 0; i < L->ops.size(); i++) {
         Op &o = L->ops[i];
@@ -288,7 +270,8 @@ void fuse_f2(int n, Lowered *L, std::vector<int> *ep, const FuseConfig &cfg, boo
 }
 
 // Level 5: cost-driven merge into operators of up to max_width qubits.
-void fuse_width(int n, Lowered *L, std::vector<int> *ep, const FuseConfig &cfg) {
+void fuse_width(int n, Lowered *L, const FuseConfig &cfg) {
+    const std::vector<int> *ep = &L->op_epoch;
     const double tol = 1e-14;
     std::vector<Op> out;
     std::vector<int> out_terms, out_ep;
@@ -334,11 +317,7 @@ void fuse_width(int n, Lowered *L, std::vector<int> *ep, const FuseConfig &cfg) 
         }
     }
     L->ops.swap(out);
-    *ep = out_ep;
-    std::vector<int> fences;
-    for (size_t i = 1; i < out_ep.size(); i++)
-        if (out_ep[i] != out_ep[i - 1]) fences.push_back(int(i) - 1);
-    L->fence_after.swap(fences);
+    L->op_epoch.swap(out_ep);
 }
 
 }  // namespace
@@ -346,25 +325,24 @@ void fuse_width(int n, Lowered *L, std::vector<int> *ep, const FuseConfig &cfg) 
 void fuse(int n, Lowered *L, const FuseConfig &cfg, int64_t counts[6]) {
     for (int l = 0; l < 6; l++) counts[l] = -1;
     counts[0] = int64_t(L->ops.size());
-    std::vector<int> ep = epochs(*L);
-    if (cfg.level >= 1) { fuse_f1(n, L, &ep, cfg); counts[1] = int64_t(L->ops.size()); }
-    if (cfg.level >= 2) { fuse_f3(n, L, &ep, cfg); counts[2] = int64_t(L->ops.size()); }
+    if (cfg.level >= 1) { fuse_f1(n, L, cfg); counts[1] = int64_t(L->ops.size()); }
+    if (cfg.level >= 2) { fuse_f3(n, L, cfg); counts[2] = int64_t(L->ops.size()); }
     if (cfg.level == 3) {
         // without SWAP normalisation a pair merges only with a pair that the
         // gates named in the same order
         std::vector<int> orient(L->ops.size(), 0);
         for (size_t i = 0; i < L->ops.size(); i++) orient[i] = L->ops[i].orient;
-        fuse_f2(n, L, &ep, cfg, true, orient);
-        compact(L, &ep);
+        fuse_f2(n, L, cfg, true, orient);
+        compact(L);
         counts[3] = int64_t(L->ops.size());
     }
     if (cfg.level >= 4) {
         std::vector<int> none;
-        fuse_f2(n, L, &ep, cfg, false, none);
-        compact(L, &ep);
+        fuse_f2(n, L, cfg, false, none);
+        compact(L);
         counts[3] = counts[4] = int64_t(L->ops.size());
     }
-    if (cfg.level >= 5) { fuse_width(n, L, &ep, cfg); counts[5] = int64_t(L->ops.size()); }
+    if (cfg.level >= 5) { fuse_width(n, L, cfg); counts[5] = int64_t(L->ops.size()); }
 }
 
 }  // namespace qs

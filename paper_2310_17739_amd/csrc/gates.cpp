@@ -131,11 +131,12 @@ int kind_arity(int kind) {
     }
 }
 
-// Rotation kinds whose matrix is cos(theta/2) A + sin(theta/2) B.
+// Rotation kinds whose matrix is cos(theta/2) A + sin(theta/2) B.  (Controlled
+// rotations are affine, not linear, in these: their control-off block is
+// constant.)
 bool is_half_angle_linear(int kind) {
     switch (kind) {
-    case QSIM_G_RX: case QSIM_G_RY: case QSIM_G_RZ: case QSIM_G_CRX: case QSIM_G_CRY:
-    case QSIM_G_CRZ: case QSIM_G_RXX: case QSIM_G_RZZ: return true;
+    case QSIM_G_RX: case QSIM_G_RY: case QSIM_G_RZ: case QSIM_G_RXX: case QSIM_G_RZZ: return true;
     default: return false;
     }
 }
@@ -211,20 +212,36 @@ void to_sorted(const int *qs, int k, const cd *src, int nblocks, Op *op) {
 }  // namespace
 
 int lower(int n, const qsim_gate *g, size_t ng, const double *mats, const double *params,
-          bool keep_params, Lowered *out) {
+          bool keep_params, bool allow_meas, Lowered *out) {
     out->ops.clear();
-    out->fence_after.clear();
+    out->op_epoch.clear();
+    out->meas.clear();
     out->input_gates = 0;
     out->ops.reserve(ng);
+    out->op_epoch.reserve(ng);
+    int epoch = 0;
     std::vector<cd> m, m2;
     for (size_t i = 0; i < ng; i++) {
         const qsim_gate &gi = g[i];
         if (gi.kind == QSIM_G_BARRIER) {
-            out->fence_after.push_back(int(out->ops.size()) - 1);
+            epoch++;
             continue;
         }
-        if (gi.kind == QSIM_G_MEASURE || gi.kind == QSIM_G_RESET || gi.kind == QSIM_G_ASSERT0)
-            return QSIM_E_UNSUPPORTED;
+        if (gi.kind == QSIM_G_MEASURE || gi.kind == QSIM_G_RESET || gi.kind == QSIM_G_ASSERT0) {
+            if (!allow_meas) return QSIM_E_UNSUPPORTED;
+            if (gi.nq != 1) return QSIM_E_ARG;
+            if (gi.q[0] < 0 || gi.q[0] >= n) return QSIM_E_QUBIT;
+            if (gi.kind != QSIM_G_RESET && gi.slot < 0) return QSIM_E_ARG;
+            MeasRec r;
+            r.epoch = epoch;
+            r.kind = gi.kind == QSIM_G_MEASURE ? DEVOP_MEASURE
+                     : gi.kind == QSIM_G_ASSERT0 ? DEVOP_ASSERT0 : DEVOP_RESET;
+            r.q = gi.q[0];
+            r.slot = gi.kind == QSIM_G_RESET ? 0 : gi.slot;
+            out->meas.push_back(r);
+            epoch++;
+            continue;
+        }
         int k = gi.nq;
         if (k < 1 || k > kMaxK) return QSIM_E_ARG;
         if (gi.kind != QSIM_G_MAT && kind_arity(gi.kind) != k)
@@ -277,8 +294,10 @@ int lower(int n, const qsim_gate *g, size_t ng, const double *mats, const double
             to_sorted(gi.q, k, m.data(), 1, &op);
         }
         out->ops.push_back(std::move(op));
+        out->op_epoch.push_back(epoch);
         out->input_gates++;
     }
+    out->n_epochs = epoch + 1;
     return QSIM_OK;
 }
 

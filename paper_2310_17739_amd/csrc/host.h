@@ -42,10 +42,22 @@ struct Op {
     }
 };
 
-// Circuit element after lowering: an operator, or a fence.
+// A measurement, assertion or reset record of a program: it runs after the
+// operators of epoch `epoch` and before those of epoch + 1.
+struct MeasRec {
+    int epoch = 0;
+    int kind = 0;   // DEVOP_MEASURE, DEVOP_ASSERT0 or DEVOP_RESET
+    int q = 0;
+    int slot = 0;
+};
+
+// A lowered circuit: operators in order, each with its epoch (barriers and
+// measurement records start a new epoch; fusion never crosses epochs).
 struct Lowered {
     std::vector<Op> ops;
-    std::vector<int> fence_after;   // op indices after which a barrier sits
+    std::vector<int> op_epoch;
+    std::vector<MeasRec> meas;
+    int n_epochs = 1;
     int64_t input_gates = 0;
 };
 
@@ -59,8 +71,9 @@ struct FuseConfig {
 
 // ---- lowering (gates.cpp)
 // Returns QSIM_OK or an error; fills `out`.  Gate matrices are built in FP64.
+// Measurement records are accepted only with `allow_meas`.
 int lower(int n, const qsim_gate *g, size_t ng, const double *mats,
-          const double *params, bool keep_params, Lowered *out);
+          const double *params, bool keep_params, bool allow_meas, Lowered *out);
 // Dense matrix of one gate record on its own qubits in record order.
 int gate_matrix(const qsim_gate &g, const double *theta, std::vector<cd> *m);
 
@@ -75,6 +88,11 @@ double max_abs(const cd *m, size_t n);
 
 // ---- planning (plan.cpp)
 struct Pass {
+    enum Kind { TILE = 0, STRIDED = 1, MEASURE = 2 };
+    int kind = TILE;
+    MeasRec meas;                 // MEASURE passes (tiled programs)
+    std::vector<MeasRec> inline_meas;   // resident passes: records after ops[inline_at[i]] ...
+    std::vector<int> seq;         // resident passes: order of items, >= 0 op index, < 0 ~meas index
     int t = 0;                    // tile qubits
     int c = 0;                    // contiguous low qubits (0..c-1) in the tile
     uint64_t tile_mask = 0;       // all tile qubits
@@ -94,10 +112,11 @@ struct PlanConfig {
 };
 
 // meta_bytes[i]: LDS bytes operator i needs in a tiled pass (record +
-// coefficients at the state precision).
-void plan_passes(int n, const std::vector<Op> &ops, const std::vector<int> &fence_after,
-                 const std::vector<uint32_t> &meta_bytes, const PlanConfig &cfg,
-                 std::vector<Pass> *passes);
+// coefficients at the state precision).  Measurement records of L.meas are
+// placed between epochs: inside resident passes (t == n) as records, as
+// passes of their own otherwise.
+void plan_passes(int n, const Lowered &L, const std::vector<uint32_t> &meta_bytes,
+                 const PlanConfig &cfg, std::vector<Pass> *passes);
 
 // ---- packing into device tables (plan.cpp)
 // Device operator record (16 bytes): see kernels.hip.
@@ -118,6 +137,8 @@ struct PackedPlan {
     std::vector<uint32_t> pass_begin;   // op range of pass i: [pass_begin[i], pass_begin[i+1])
     std::vector<uint32_t> coef_begin;   // coefficient range of pass i, likewise
     std::vector<cd> coefs;              // FP64 coefficients; cast on upload
+    std::vector<int8_t> op_np;          // per record: angle slots of its operator
+    std::vector<int32_t> op_slots;      // per record: 3 slot indices
     int64_t terms = 0;
 };
 

@@ -263,6 +263,7 @@ __global__ void __launch_bounds__(NT) k_tile(Cx<T> *__restrict__ state, uint64_t
     const Cx<T> *cfg = coefs + size_t(b) * cstride + cb;
     const int tid = threadIdx.x;
     const bool active = (E > 1) || (tid < TN);
+    if (ma.status && ma.status[b] != 0) return;   // an earlier step of this state failed
 
     // operator records and coefficients of the pass: first into registers
     constexpr int MR = 4;   // records / coefficients per thread held across the tile loads
@@ -337,9 +338,9 @@ __global__ void __launch_bounds__(NT) k_tile(Cx<T> *__restrict__ state, uint64_t
         __syncthreads();
         if (status) break;
     }
-    if (ma.status && tid == 0) {
+    if (status && ma.status && tid == 0) {
         ma.status[b] = status;
-        if (ma.fail_at) ma.fail_at[b] = status ? int(ob) + i : -1;
+        if (ma.fail_at) ma.fail_at[b] = int(ob) + i;
     }
     if (!(flags & TF_NO_STORE)) {
 #pragma unroll
@@ -359,9 +360,12 @@ __global__ void __launch_bounds__(NT) k_tile(Cx<T> *__restrict__ state, uint64_t
 // --------------------------------------------------------- strided sweep
 template <typename T, int K>
 __global__ void __launch_bounds__(NT) k_sweep(Cx<T> *__restrict__ state, uint64_t sstride, int n,
-                                              DevOp op, const Cx<T> *__restrict__ cf) {
+                                              DevOp op, const Cx<T> *__restrict__ cf,
+                                              uint64_t cstride, const int32_t *__restrict__ status) {
     constexpr int D = 1 << K;
+    if (status && status[blockIdx.y] != 0) return;
     Cx<T> *st = state + size_t(blockIdx.y) * sstride;
+    cf += size_t(blockIdx.y) * cstride;
     int p[K];
 #pragma unroll
     for (int j = 0; j < K; j++) p[j] = op.pos[j];
@@ -474,6 +478,100 @@ __global__ void __launch_bounds__(NT) k_finish(const double *__restrict__ partia
     if (threadIdx.x == 0) out[blockIdx.x] = acc[0];
 }
 
+// ------------------------------------------------- batched measurement
+// Measurement, assertion or reset of qubit q in every state of a batch whose
+// state does not fit one tile: P0, P1 come from a marginal reduction
+// (p01[2b], p01[2b+1]); every thread takes the same decision from them and
+// updates its amplitude pairs (x, x | 2^q).
+template <typename T>
+__global__ void __launch_bounds__(NT) k_decide(Cx<T> *__restrict__ state, uint64_t sstride, int n,
+                                               int q, int kind, int slot,
+                                               const double *__restrict__ p01, MeasArgs ma) {
+    const uint32_t b = blockIdx.y;
+    if (ma.status && ma.status[b] != 0) return;
+    const double P0 = p01[2 * b], P1 = p01[2 * b + 1];
+    int o = 0, fail = 0;
+    bool swap = false, touch = true;
+    double kept = 1.0;
+    const size_t idx = size_t(b) * ma.nslots + slot;
+    if (kind == qs::DEVOP_RESET) {
+        if (P1 == 0.0) touch = false;
+        else if (P0 == 0.0) swap = true;
+        else fail = QSIM_E_NOT_DEFINITE;
+    } else {
+        if (kind == qs::DEVOP_ASSERT0) {
+            if (!(P0 > 0.0)) fail = QSIM_E_ZERO_PROB;
+        } else if (ma.forced && ma.forced[idx] >= 0) {
+            o = ma.forced[idx];
+            if (!((o ? P1 : P0) > 0.0)) fail = QSIM_E_ZERO_PROB;
+        } else {
+            o = (ma.uniforms[idx] < P0 / (P0 + P1)) ? 0 : 1;
+        }
+        kept = o ? P1 : P0;
+    }
+    if (fail) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ma.status[b] = fail;
+            if (ma.fail_at) ma.fail_at[b] = -2 - slot;
+        }
+        return;
+    }
+    if (kind != qs::DEVOP_RESET && blockIdx.x == 0 && threadIdx.x == 0) {
+        ma.outcomes[idx] = o;
+        ma.probs[idx] = kept / (P0 + P1);
+    }
+    if (!touch) return;
+    const T scale = T(1.0 / sqrt(kept));
+    Cx<T> *st = state + size_t(b) * sstride;
+    const uint64_t half = uint64_t(1) << (n - 1), bq = uint64_t(1) << q;
+    for (uint64_t g = uint64_t(blockIdx.x) * NT + threadIdx.x; g < half; g += uint64_t(gridDim.x) * NT) {
+        const uint64_t x0 = ((g >> q) << (q + 1)) | (g & (bq - 1)), x1 = x0 | bq;
+        const Cx<T> a0 = st[x0], a1 = st[x1];
+        Cx<T> n0, n1 = Cx<T>{T(0), T(0)};
+        if (swap) n0 = a1;
+        else if (o == 0) n0 = Cx<T>{a0.re * scale, a0.im * scale};
+        else { n0 = Cx<T>{T(0), T(0)}; n1 = Cx<T>{a1.re * scale, a1.im * scale}; }
+        st[x0] = n0;
+        st[x1] = n1;
+    }
+}
+
+// Per-state operator coefficients of a parameterised template: entry e
+// covers `count` coefficients; with np angle slots its template holds 2^np
+// blocks, block s weighted by prod_j (bit j of s ? sin : cos)(theta_slot_j / 2).
+template <typename T>
+__global__ void __launch_bounds__(NT) k_bind(const double *__restrict__ tmpl,
+                                             const BindEntry *__restrict__ ents,
+                                             const double *__restrict__ params, int nparams,
+                                             Cx<T> *__restrict__ out, uint64_t cstride,
+                                             uint32_t nstates) {
+    const BindEntry e = ents[blockIdx.x];
+    const uint64_t total = uint64_t(nstates) * e.count;
+    for (uint64_t idx = uint64_t(blockIdx.y) * NT + threadIdx.x; idx < total;
+         idx += uint64_t(gridDim.y) * NT) {
+        const uint32_t b = uint32_t(idx / e.count), c = uint32_t(idx % e.count);
+        double cs[3], sn[3];
+        for (int j = 0; j < e.np; j++) {
+            const double th = params[size_t(b) * nparams + e.slot[j]];
+            cs[j] = cos(0.5 * th);
+            sn[j] = sin(0.5 * th);
+        }
+        double re = 0.0, im = 0.0;
+        for (int sb = 0; sb < (1 << e.np); sb++) {
+            double w = 1.0;
+            for (int j = 0; j < e.np; j++) w *= ((sb >> j) & 1) ? sn[j] : cs[j];
+            const size_t src = 2 * (size_t(e.tmpl_off) + size_t(sb) * e.count + c);
+            re += w * tmpl[src];
+            im += w * tmpl[src + 1];
+        }
+        out[size_t(b) * cstride + e.bound_off + c] = Cx<T>{T(re), T(im)};
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_fill_i32(int32_t *__restrict__ p, int32_t v, uint64_t n) {
+    for (uint64_t i = uint64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += uint64_t(gridDim.x) * NT) p[i] = v;
+}
+
 // ------------------------------------------------------------- launchers
 namespace {
 int check(hipError_t e) { return note_hip(e, "kernel launch"); }
@@ -570,24 +668,25 @@ int launch_tile(int dtype, void *state, uint64_t sstride, uint32_t nstates, cons
 
 template <typename T>
 static void sweep_t(Cx<T> *state, uint64_t sstride, uint32_t nstates, int n, const DevOp &op,
-                    const Cx<T> *cf, hipStream_t st) {
+                    const Cx<T> *cf, uint64_t cstride, const int32_t *status, hipStream_t st) {
     const dim3 grid(grid_for(uint64_t(1) << (n - op.k)), nstates);
     switch (op.k) {
-    case 1: hipLaunchKernelGGL((k_sweep<T, 1>), grid, dim3(NT), 0, st, state, sstride, n, op, cf); break;
-    case 2: hipLaunchKernelGGL((k_sweep<T, 2>), grid, dim3(NT), 0, st, state, sstride, n, op, cf); break;
-    case 3: hipLaunchKernelGGL((k_sweep<T, 3>), grid, dim3(NT), 0, st, state, sstride, n, op, cf); break;
-    case 4: hipLaunchKernelGGL((k_sweep<T, 4>), grid, dim3(NT), 0, st, state, sstride, n, op, cf); break;
-    default: hipLaunchKernelGGL((k_sweep<T, 5>), grid, dim3(NT), 0, st, state, sstride, n, op, cf); break;
+    case 1: hipLaunchKernelGGL((k_sweep<T, 1>), grid, dim3(NT), 0, st, state, sstride, n, op, cf, cstride, status); break;
+    case 2: hipLaunchKernelGGL((k_sweep<T, 2>), grid, dim3(NT), 0, st, state, sstride, n, op, cf, cstride, status); break;
+    case 3: hipLaunchKernelGGL((k_sweep<T, 3>), grid, dim3(NT), 0, st, state, sstride, n, op, cf, cstride, status); break;
+    case 4: hipLaunchKernelGGL((k_sweep<T, 4>), grid, dim3(NT), 0, st, state, sstride, n, op, cf, cstride, status); break;
+    default: hipLaunchKernelGGL((k_sweep<T, 5>), grid, dim3(NT), 0, st, state, sstride, n, op, cf, cstride, status); break;
     }
 }
 
 int launch_sweep(int dtype, void *state, uint64_t sstride, uint32_t nstates, int n,
-                 const DevOp &op, const void *coefs, hipStream_t st) {
+                 const DevOp &op, const void *coefs, hipStream_t st, uint64_t cstride,
+                 const int32_t *status) {
     if (op.k < 1 || op.k > 5 || op.k > n) return QSIM_E_ARG;
     if (dtype == QSIM_C64)
-        sweep_t<float>((Cx<float> *)state, sstride, nstates, n, op, (const Cx<float> *)coefs, st);
+        sweep_t<float>((Cx<float> *)state, sstride, nstates, n, op, (const Cx<float> *)coefs, cstride, status, st);
     else
-        sweep_t<double>((Cx<double> *)state, sstride, nstates, n, op, (const Cx<double> *)coefs, st);
+        sweep_t<double>((Cx<double> *)state, sstride, nstates, n, op, (const Cx<double> *)coefs, cstride, status, st);
     return check(hipGetLastError());
 }
 
@@ -611,7 +710,8 @@ uint32_t marginal_chunks(int n, int nqs) {
 }
 
 int launch_marginal(int dtype, const void *state, uint64_t sstride, uint32_t nstates, int n,
-                    const int *qs, int nqs, double *partials, double *out, hipStream_t st) {
+                    const int *qs, int nqs, double *partials, double *out, hipStream_t st,
+                    uint32_t nchunks_override) {
     if (nqs < 0 || nqs > 12 || nqs > n) return QSIM_E_ARG;
     MargArgs a{};
     a.n = n;
@@ -620,7 +720,8 @@ int launch_marginal(int dtype, const void *state, uint64_t sstride, uint32_t nst
     for (int i = 0; i < nqs; i++)
         for (int j = i + 1; j < nqs; j++)
             if (a.sorted[j] < a.sorted[i]) { int t = a.sorted[i]; a.sorted[i] = a.sorted[j]; a.sorted[j] = t; }
-    const uint32_t nchunks = marginal_chunks(n, nqs);
+    uint32_t nchunks = marginal_chunks(n, nqs);
+    if (nchunks_override && nchunks_override < nchunks) nchunks = nchunks_override;
     const dim3 grid(nchunks, 1u << nqs, nstates);
     if (dtype == QSIM_C64)
         hipLaunchKernelGGL(k_marginal<float>, grid, dim3(NT), 0, st, (const Cx<float> *)state, sstride, a, partials);
@@ -639,9 +740,10 @@ uint32_t pauli_chunks(int n) {
 
 int launch_pauli(int dtype, const void *state, uint64_t sstride, uint32_t nstates, int n,
                  const uint64_t *xmask, const uint64_t *zmask, int nterms, double *partials,
-                 double *out, hipStream_t st) {
+                 double *out, hipStream_t st, uint32_t nchunks_override) {
     if (nterms <= 0) return QSIM_OK;
-    const uint32_t nchunks = pauli_chunks(n);
+    uint32_t nchunks = pauli_chunks(n);
+    if (nchunks_override && nchunks_override < nchunks) nchunks = nchunks_override;
     const dim3 grid(nchunks, uint32_t(nterms), nstates);
     if (dtype == QSIM_C64)
         hipLaunchKernelGGL(k_pauli<float>, grid, dim3(NT), 0, st, (const Cx<float> *)state, sstride, n, xmask, zmask, partials);
@@ -649,6 +751,35 @@ int launch_pauli(int dtype, const void *state, uint64_t sstride, uint32_t nstate
         hipLaunchKernelGGL(k_pauli<double>, grid, dim3(NT), 0, st, (const Cx<double> *)state, sstride, n, xmask, zmask, partials);
     hipLaunchKernelGGL(k_finish, dim3(uint32_t(nstates) * uint32_t(nterms) * 2), dim3(NT), 0, st,
                        partials, nchunks, out);
+    return check(hipGetLastError());
+}
+
+int launch_decide(int dtype, void *state, uint64_t sstride, uint32_t nstates, int n, int q,
+                  int kind, int slot, const double *p01, const MeasArgs &ma, hipStream_t st) {
+    const dim3 grid(grid_for(uint64_t(1) << (n - 1)) > 1024 ? 1024 : grid_for(uint64_t(1) << (n - 1)), nstates);
+    if (dtype == QSIM_C64)
+        hipLaunchKernelGGL(k_decide<float>, grid, dim3(NT), 0, st, (Cx<float> *)state, sstride, n, q, kind, slot, p01, ma);
+    else
+        hipLaunchKernelGGL(k_decide<double>, grid, dim3(NT), 0, st, (Cx<double> *)state, sstride, n, q, kind, slot, p01, ma);
+    return check(hipGetLastError());
+}
+
+int launch_bind(int dtype, const double *tmpl, const BindEntry *ents, uint32_t nents,
+                const double *params, int nparams, void *out, uint64_t cstride, uint32_t nstates,
+                uint32_t max_count, hipStream_t st) {
+    if (nents == 0) return QSIM_OK;
+    uint64_t per = (uint64_t(nstates) * max_count + NT - 1) / NT;
+    const dim3 grid(nents, uint32_t(per > 256 ? 256 : (per ? per : 1)));
+    if (dtype == QSIM_C64)
+        hipLaunchKernelGGL(k_bind<float>, grid, dim3(NT), 0, st, tmpl, ents, params, nparams, (Cx<float> *)out, cstride, nstates);
+    else
+        hipLaunchKernelGGL(k_bind<double>, grid, dim3(NT), 0, st, tmpl, ents, params, nparams, (Cx<double> *)out, cstride, nstates);
+    return check(hipGetLastError());
+}
+
+int launch_fill_i32(int32_t *p, int32_t v, uint64_t n, hipStream_t st) {
+    if (n == 0) return QSIM_OK;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(NT), 0, st, p, v, n);
     return check(hipGetLastError());
 }
 

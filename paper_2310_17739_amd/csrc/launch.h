@@ -54,9 +54,33 @@ int launch_tile(int dtype, void *state, uint64_t sstride, uint32_t nstates, cons
                 uint32_t ce, uint64_t cstride, const MeasArgs *ma, uint32_t flags,
                 hipStream_t st);
 
-// One operator over the whole state (positions are global qubits).
+// One operator over the whole state (positions are global qubits); the
+// coefficients of state b start at coefs + b * cstride; states whose status
+// is nonzero are skipped.
 int launch_sweep(int dtype, void *state, uint64_t sstride, uint32_t nstates, int n,
-                 const qs::DevOp &op, const void *coefs, hipStream_t st);
+                 const qs::DevOp &op, const void *coefs, hipStream_t st, uint64_t cstride = 0,
+                 const int32_t *status = nullptr);
+
+// Measurement / assertion / reset of qubit q in every state of a batch from
+// per-state weights p01[2b], p01[2b+1] (a marginal reduction), decided on
+// the device (kind: qs::DEVOP_*).
+int launch_decide(int dtype, void *state, uint64_t sstride, uint32_t nstates, int n, int q,
+                  int kind, int slot, const double *p01, const MeasArgs &ma, hipStream_t st);
+
+// Binding of parameterised operator coefficients (see k_bind).
+struct BindEntry {
+    uint32_t bound_off;   // offset in a state's bound coefficient array (elements)
+    uint32_t count;       // coefficients of the operator (terms * 2^k)
+    uint32_t tmpl_off;    // offset of block 0 in the FP64 template (complex elements)
+    int32_t np;           // angle slots (0..3)
+    int32_t slot[3];
+    int32_t pad;
+};
+int launch_bind(int dtype, const double *tmpl, const BindEntry *ents, uint32_t nents,
+                const double *params, int nparams, void *out, uint64_t cstride, uint32_t nstates,
+                uint32_t max_count, hipStream_t st);
+
+int launch_fill_i32(int32_t *p, int32_t v, uint64_t n, hipStream_t st);
 
 // |0...0> in every state of a batch.
 int launch_init_zero(int dtype, void *state, uint64_t sstride, uint32_t nstates, int n,
@@ -67,7 +91,8 @@ int launch_init_zero(int dtype, void *state, uint64_t sstride, uint32_t nstates,
 // Writes partial sums to `partials` ([nstates][2^nqs][nchunks]) and the
 // final sums to `out` ([nstates][2^nqs]).
 int launch_marginal(int dtype, const void *state, uint64_t sstride, uint32_t nstates, int n,
-                    const int *qs, int nqs, double *partials, double *out, hipStream_t st);
+                    const int *qs, int nqs, double *partials, double *out, hipStream_t st,
+                    uint32_t nchunks = 0);
 uint32_t marginal_chunks(int n, int nqs);
 
 // Pauli-term overlaps S_k = sum_x (-1)^{popcount(x & z_k)} conj(a[x ^ x_k]) a[x]
@@ -75,7 +100,7 @@ uint32_t marginal_chunks(int n, int nqs);
 // out[(b * nterms + k) * 2 + {0,1}].
 int launch_pauli(int dtype, const void *state, uint64_t sstride, uint32_t nstates, int n,
                  const uint64_t *xmask, const uint64_t *zmask, int nterms, double *partials,
-                 double *out, hipStream_t st);
+                 double *out, hipStream_t st, uint32_t nchunks = 0);
 uint32_t pauli_chunks(int n);
 
 // Keep the half with bit q == outcome, scale it by `scale`, zero the other.

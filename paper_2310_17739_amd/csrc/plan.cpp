@@ -20,87 +20,106 @@
 
 namespace qs {
 
-void plan_passes(int n, const std::vector<Op> &ops, const std::vector<int> &fence_after,
-                 const std::vector<uint32_t> &meta_bytes, const PlanConfig &cfg,
-                 std::vector<Pass> *passes) {
+void plan_passes(int n, const Lowered &L, const std::vector<uint32_t> &meta_bytes,
+                 const PlanConfig &cfg, std::vector<Pass> *passes) {
     passes->clear();
+    const std::vector<Op> &ops = L.ops;
     const int N = int(ops.size());
-    if (N == 0) return;
     const int t = std::min(cfg.tile_qubits, n);
     const int c = std::min(cfg.low_qubits, t);
     const uint64_t all = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
     const uint64_t low = (uint64_t(1) << c) - 1;
+    constexpr uint32_t kMeasBytes = 16;
 
-    // fences split the list into independent segments
-    std::vector<int> seg_end;
-    {
-        std::vector<int> f = fence_after;
-        std::sort(f.begin(), f.end());
-        for (int x : f)
-            if (x >= 0 && x < N - 1 && (seg_end.empty() || seg_end.back() != x + 1)) seg_end.push_back(x + 1);
-        seg_end.push_back(N);
-    }
+    // operators of epoch e: [ep_begin[e], ep_begin[e + 1])
+    std::vector<int> ep_begin(L.n_epochs + 1, N);
+    for (int i = N - 1; i >= 0; i--) ep_begin[L.op_epoch[i]] = i;
+    for (int e = L.n_epochs - 1; e >= 0; e--)
+        if (ep_begin[e] > ep_begin[e + 1]) ep_begin[e] = ep_begin[e + 1];
+    // measurement records after epoch e: [mb[e], mb[e + 1])
+    std::vector<int> mb(L.n_epochs + 1, int(L.meas.size()));
+    for (int i = int(L.meas.size()) - 1; i >= 0; i--) mb[L.meas[i].epoch] = i;
+    for (int e = L.n_epochs - 1; e >= 0; e--)
+        if (mb[e] > mb[e + 1]) mb[e] = mb[e + 1];
 
-    auto finish = [&](uint64_t T, std::vector<int> &&sel, bool strided) {
+    auto tile_pass = [&](uint64_t T) {
         Pass p;
-        p.strided = strided;
-        if (!strided) {
-            // pad the tile to exactly t qubits with the lowest unused qubits
-            for (int q = 0; q < n && __builtin_popcountll(T) < t; q++) T |= uint64_t(1) << q;
-            p.t = t;
-            p.c = c;
-            p.tile_mask = T;
-            for (int q = c; q < n; q++)
-                if ((T >> q) & 1) p.hi[p.nhi++] = q;
-        }
-        p.ops = std::move(sel);
+        p.kind = Pass::TILE;
+        // pad the tile to exactly t qubits with the lowest unused qubits
+        for (int q = 0; q < n && __builtin_popcountll(T) < t; q++) T |= uint64_t(1) << q;
+        p.t = t;
+        p.c = c;
+        p.tile_mask = T;
+        for (int q = c; q < n; q++)
+            if ((T >> q) & 1) p.hi[p.nhi++] = q;
+        return p;
+    };
+    auto strided = [&](int i) {
+        Pass p;
+        p.kind = Pass::STRIDED;
+        p.strided = true;
+        p.ops = {i};
         passes->push_back(std::move(p));
     };
 
     if (cfg.one_op_per_pass) {
-        for (int i = 0; i < N; i++) finish(0, {i}, true);
-        return;
-    }
-    if (t >= n) {
-        // the whole state fits one tile: one pass per segment, with operators
-        // too wide for the tile kernel as sweeps of their own
-        int b = 0;
-        for (int e : seg_end) {
-            std::vector<int> sel;
-            size_t meta = 0;
-            for (int i = b; i < e; i++) {
-                if (ops[i].k > cfg.max_tile_k) {
-                    if (!sel.empty()) finish(all, std::move(sel), false);
-                    sel.clear();
-                    meta = 0;
-                    finish(0, {i}, true);
-                    continue;
-                }
-                if (!sel.empty() && meta + meta_bytes[i] > cfg.meta_budget) {
-                    finish(all, std::move(sel), false);
-                    sel.clear();
-                    meta = 0;
-                }
-                sel.push_back(i);
-                meta += meta_bytes[i];
+        for (int e = 0; e < L.n_epochs; e++) {
+            for (int i = ep_begin[e]; i < ep_begin[e + 1]; i++) strided(i);
+            for (int m = mb[e]; m < mb[e + 1]; m++) {
+                Pass p;
+                p.kind = Pass::MEASURE;
+                p.meas = L.meas[m];
+                passes->push_back(std::move(p));
             }
-            if (!sel.empty()) finish(all, std::move(sel), false);
-            b = e;
         }
         return;
     }
 
-    // doubly linked list of pending operators
+    if (t >= n) {
+        // The whole state is one tile: resident passes run operators and
+        // measurement records in program order, split where the records and
+        // coefficients outgrow the LDS budget; operators too wide for the
+        // tile kernel run as sweeps of their own.
+        Pass cur = tile_pass(all);
+        size_t meta = 0;
+        auto flush = [&]() {
+            if (!cur.seq.empty()) passes->push_back(std::move(cur));
+            cur = tile_pass(all);
+            meta = 0;
+        };
+        for (int e = 0; e < L.n_epochs; e++) {
+            for (int i = ep_begin[e]; i < ep_begin[e + 1]; i++) {
+                if (ops[i].k > cfg.max_tile_k) {
+                    flush();
+                    strided(i);
+                    continue;
+                }
+                if (!cur.seq.empty() && meta + meta_bytes[i] > cfg.meta_budget) flush();
+                cur.ops.push_back(i);
+                cur.seq.push_back(i);
+                meta += meta_bytes[i];
+            }
+            for (int m = mb[e]; m < mb[e + 1]; m++) {
+                if (!cur.seq.empty() && meta + kMeasBytes > cfg.meta_budget) flush();
+                cur.seq.push_back(~int(cur.inline_meas.size()));
+                cur.inline_meas.push_back(L.meas[m]);
+                meta += kMeasBytes;
+            }
+        }
+        flush();
+        return;
+    }
+
+    // doubly linked list of pending operators of one epoch
     std::vector<int> nxt(N + 1), prv(N + 1);
-    int seg_begin = 0;
-    for (int e : seg_end) {
-        // list over [seg_begin, e): head sentinel = N
-        int head = N;
-        nxt[head] = seg_begin < e ? seg_begin : head;
-        prv[head] = e - 1 >= seg_begin ? e - 1 : head;
-        for (int i = seg_begin; i < e; i++) {
-            nxt[i] = (i + 1 < e) ? i + 1 : head;
-            prv[i] = (i > seg_begin) ? i - 1 : head;
+    const int head = N;
+    for (int e = 0; e < L.n_epochs; e++) {
+        const int b = ep_begin[e], en = ep_begin[e + 1];
+        nxt[head] = b < en ? b : head;
+        prv[head] = en - 1 >= b ? en - 1 : head;
+        for (int i = b; i < en; i++) {
+            nxt[i] = (i + 1 < en) ? i + 1 : head;
+            prv[i] = (i > b) ? i - 1 : head;
         }
         while (nxt[head] != head) {
             const int first = nxt[head];
@@ -108,7 +127,7 @@ void plan_passes(int n, const std::vector<Op> &ops, const std::vector<int> &fenc
                 // too wide for the tile kernel at this precision: its own sweep
                 nxt[head] = nxt[first];
                 prv[nxt[first]] = head;
-                finish(0, {first}, true);
+                strided(first);
                 continue;
             }
             uint64_t T = low, blocked = 0;
@@ -133,9 +152,17 @@ void plan_passes(int n, const std::vector<Op> &ops, const std::vector<int> &fenc
                 nxt[prv[i]] = nxt[i];
                 prv[nxt[i]] = prv[i];
             }
-            finish(T, std::move(sel), false);
+            Pass p = tile_pass(T);
+            p.ops = std::move(sel);
+            p.seq = p.ops;
+            passes->push_back(std::move(p));
         }
-        seg_begin = e;
+        for (int m = mb[e]; m < mb[e + 1]; m++) {
+            Pass p;
+            p.kind = Pass::MEASURE;
+            p.meas = L.meas[m];
+            passes->push_back(std::move(p));
+        }
     }
 }
 
@@ -159,11 +186,27 @@ void pack_plan(const std::vector<Op> &ops, const std::vector<uint32_t> &present_
     out->pass_begin.clear();
     out->coef_begin.clear();
     out->coefs.clear();
+    out->op_np.clear();
+    out->op_slots.clear();
     out->terms = 0;
     for (const Pass &p : passes) {
         out->pass_begin.push_back(uint32_t(out->ops.size()));
         out->coef_begin.push_back(uint32_t(out->coefs.size()));
-        for (int idx : p.ops) {
+        const std::vector<int> &items = p.seq.empty() ? p.ops : p.seq;
+        for (int idx : items) {
+            if (idx < 0) {
+                const MeasRec &mr = p.inline_meas[~idx];
+                DevOp r{};
+                r.coef = uint32_t(mr.slot);
+                r.present = 0;
+                r.k = 1;
+                r.pos[0] = uint8_t(mr.q);
+                r.kind = uint8_t(mr.kind);
+                out->ops.push_back(r);
+                out->op_np.push_back(0);
+                for (int j = 0; j < 3; j++) out->op_slots.push_back(-1);
+                continue;
+            }
             const Op &o = ops[idx];
             const int d = o.dim();
             const size_t blk = size_t(d) * d;
@@ -196,6 +239,8 @@ void pack_plan(const std::vector<Op> &ops, const std::vector<uint32_t> &present_
                 }
             out->terms += __builtin_popcount(present);
             out->ops.push_back(r);
+            out->op_np.push_back(int8_t(o.np));
+            for (int j = 0; j < 3; j++) out->op_slots.push_back(o.slot[j]);
         }
     }
     out->pass_begin.push_back(uint32_t(out->ops.size()));

@@ -82,6 +82,12 @@ def _load():
         "qsim_program_stats": ([P, P], I),
         "qsim_program_destroy": ([P], I),
         "qsim_debug_plan": ([I, I, P, SZ, P, P, P, P], I),
+        "qsim_batch_create": ([P, I, P, P], I),
+        "qsim_batch_run": ([P, P], I),
+        "qsim_batch_results": ([P, I, P, P, P, P, P], I),
+        "qsim_batch_get_state": ([P, I, I, P], I),
+        "qsim_batch_info_get": ([P, P], I),
+        "qsim_batch_destroy": ([P], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -92,26 +98,38 @@ def _load():
 
 
 def _bind_optional(lib):
-    """Entry points of the batched and served forms (declared in qsim.h)."""
+    """Entry points of the served form (declared in qsim.h)."""
     P, I, SZ, D = C.c_void_p, C.c_int, C.c_size_t, C.c_double
     opt = {
-        "qsim_batch_create": ([P, I, P, P], I),
-        "qsim_batch_run": ([P, P], I),
-        "qsim_batch_results": ([P, P, P, P, P, P, P], I),
-        "qsim_batch_destroy": ([P], I),
-        "qsim_batch_info": ([P, P], I),
         "qsim_server_create": ([P, P], I),
         "qsim_server_submit": ([P, P, P], I),
         "qsim_server_poll": ([P, P, I, P], I),
         "qsim_server_stats": ([P, P], I),
         "qsim_server_destroy": ([P], I),
-        "qsim_server_get_state": ([P, C.c_int64, P], I),
     }
     for name, (args, res) in opt.items():
         if hasattr(lib, name):
             f = getattr(lib, name)
             f.argtypes = args
             f.restype = res
+
+
+class qsim_batch_group(C.Structure):
+    _fields_ = [("n", C.c_int32), ("n_states", C.c_int32), ("g", C.c_void_p), ("ng", C.c_size_t),
+                ("mats", C.c_void_p), ("params", C.c_void_p), ("n_params", C.c_int32),
+                ("uniforms", C.c_void_p), ("forced", C.c_void_p), ("n_slots", C.c_int32),
+                ("terms", C.c_void_p), ("n_terms", C.c_size_t), ("dev_states", C.c_void_p)]
+
+
+class qsim_batch_opts(C.Structure):
+    _fields_ = [("dtype", C.c_int32), ("use_graph", C.c_int32), ("max_params", C.c_int32),
+                ("pad", C.c_int32), ("fuse", qsim_fuse_opts)]
+
+
+class qsim_batch_info(C.Structure):
+    _fields_ = [("states", C.c_int64), ("input_gates", C.c_int64), ("fused_ops", C.c_int64),
+                ("passes", C.c_int64), ("state_bytes", C.c_int64), ("coef_bytes", C.c_int64),
+                ("compile_seconds", C.c_double)]
 
 
 _lib = _load()
@@ -274,6 +292,101 @@ class Program:
         if getattr(self, "p", None):
             _lib.qsim_program_destroy(self.p)
             self.p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Batched programs (qsim_batch_*): each group is a dict with keys
+    n, n_states, gates, and optionally mats, params (n_states x n_params),
+    uniforms / forced (n_states x n_slots), n_slots, terms, states (a torch
+    tensor of n_states * 2^n elements to run in place)."""
+
+    def __init__(self, groups, dtype="complex64", use_graph=False, max_params=0,
+                 level=None, max_width=None, tile_qubits=None, flags=0):
+        self.dtype = QSIM_DTYPES[dtype]
+        self._keep = []
+        arr = (qsim_batch_group * len(groups))()
+        self.groups = []
+        for i, gd in enumerate(groups):
+            g = np.ascontiguousarray(gd["gates"], dtype=GATE_DTYPE)
+            n_states = int(gd["n_states"])
+            mats = gd.get("mats")
+            mats = None if mats is None else np.ascontiguousarray(mats, dtype=np.complex128)
+            params = gd.get("params")
+            params = None if params is None else np.ascontiguousarray(params, dtype=np.float64).reshape(n_states, -1)
+            n_slots = int(gd.get("n_slots", 0))
+            uni = gd.get("uniforms")
+            uni = None if uni is None else np.ascontiguousarray(uni, dtype=np.float64).reshape(n_states, n_slots)
+            forced = gd.get("forced")
+            forced = None if forced is None else np.ascontiguousarray(forced, dtype=np.int32).reshape(n_states, n_slots)
+            terms = gd.get("terms")
+            terms = None if terms is None else np.ascontiguousarray(terms, dtype=PAULI_DTYPE)
+            states = gd.get("states")
+            self._keep += [g, mats, params, uni, forced, terms, states]
+            a = arr[i]
+            a.n = int(gd["n"])
+            a.n_states = n_states
+            a.g = g.ctypes.data
+            a.ng = len(g)
+            a.mats = None if mats is None else mats.ctypes.data
+            a.params = None if params is None else params.ctypes.data
+            a.n_params = 0 if params is None else params.shape[1]
+            a.uniforms = None if uni is None else uni.ctypes.data
+            a.forced = None if forced is None else forced.ctypes.data
+            a.n_slots = n_slots
+            a.terms = None if terms is None else terms.ctypes.data
+            a.n_terms = 0 if terms is None else len(terms)
+            a.dev_states = None if states is None else states.data_ptr()
+            self.groups.append({"n": a.n, "n_states": n_states, "n_slots": n_slots})
+        o = qsim_batch_opts()
+        o.dtype = self.dtype
+        o.use_graph = int(bool(use_graph))
+        o.max_params = int(max_params)
+        fo = _opts(level, max_width, tile_qubits, flags)
+        if fo is not None:
+            o.fuse = fo
+        h = C.c_void_p()
+        check(_lib.qsim_batch_create(arr, len(groups), C.byref(o), C.byref(h)), "qsim_batch_create")
+        self.h = h
+
+    def qsim_batch_run(self, stream=None):
+        if stream is None:
+            stream = _torch().cuda.current_stream()
+        check(_lib.qsim_batch_run(self.h, C.c_void_p(stream.cuda_stream)), "qsim_batch_run")
+
+    def qsim_batch_results(self, group: int) -> dict:
+        gd = self.groups[group]
+        ns, nsl = gd["n_states"], gd["n_slots"]
+        outc = np.zeros((ns, max(nsl, 1)), dtype=np.int32)
+        probs = np.zeros((ns, max(nsl, 1)), dtype=np.float64)
+        ev = np.zeros(ns, dtype=np.float64)
+        nrm = np.zeros(ns, dtype=np.float64)
+        status = np.zeros(ns, dtype=np.int32)
+        check(_lib.qsim_batch_results(self.h, int(group), _p(outc), _p(probs), _p(ev), _p(nrm), _p(status)),
+              "qsim_batch_results")
+        return {"outcomes": outc[:, :nsl], "probs": probs[:, :nsl], "expvals": ev, "norms": nrm,
+                "status": status}
+
+    def qsim_batch_get_state(self, group: int, index: int) -> np.ndarray:
+        n = self.groups[group]["n"]
+        out = np.empty(1 << n, dtype=np.complex64 if self.dtype == C64 else np.complex128)
+        check(_lib.qsim_batch_get_state(self.h, int(group), int(index), _p(out)), "qsim_batch_get_state")
+        return out
+
+    def qsim_batch_info(self) -> dict:
+        i = qsim_batch_info()
+        check(_lib.qsim_batch_info_get(self.h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in qsim_batch_info._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.qsim_batch_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:
