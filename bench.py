@@ -50,6 +50,161 @@ def cpu_baseline(n, g, target_s=12.0):
                       f"{dt2:.1f} s wall, OpenMP over the amplitude loop"}
 
 
+def pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def run_trajectories(qsim, W, ntraj=1024, rounds=500):
+    """Mid-circuit measurement form: 12 system + 2 ancilla qubits, complex64
+    states with FP64 reductions, `rounds` rounds of gates + 2 measurements +
+    2 resets, one trajectory per state, decisions on the device."""
+    import numpy as np
+    import torch
+    g = W.trajectory_round_program(12, rounds, seed=4)
+    u = W.uniforms((ntraj, 2 * rounds), seed=5)
+    b = qsim.Batch([{"n": 14, "n_states": ntraj, "gates": g, "uniforms": u, "n_slots": 2 * rounds}],
+                   dtype="complex64", use_graph=True)
+    b.qsim_batch_run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.qsim_batch_run()
+    res = b.qsim_batch_results(0)
+    dt = time.perf_counter() - t0
+    info = b.qsim_batch_info()
+    b.close()
+    p = res["probs"]
+    return {"workload": f"{ntraj} trajectories x {rounds} rounds, 14 qubits, complex64",
+            "seconds": dt, "trajectory_rounds_per_s": ntraj * rounds / dt,
+            "input_gates_per_s": ntraj * len(g) / dt, "passes": info["passes"],
+            "failed": int((res["status"] != 0).sum()),
+            "mean_p_outcome": float(p.mean()), "norm_max_dev": float(np.abs(res["norms"] - 1).max())}
+
+
+def run_batched(qsim, W, n_circuits=4096, n_exp=500, sample_one_at_a_time=48):
+    """Batched form: circuits of width U{10..20}, each a 500-exponential
+    template with its own angles, complex64 with FP64 <H>, one graph launch;
+    against the same circuits one at a time in complex128 on the same GPU."""
+    import numpy as np
+    import torch
+    tmpl = W.batch_templates(10, 20, n_exp, 100)
+    widths, thetas = W.batch_instances(n_circuits, 10, 20, n_exp)
+    groups, index = [], []
+    for w in range(10, 21):
+        sel = np.nonzero(widths == w)[0]
+        if len(sel) == 0:
+            continue
+        g, H = tmpl[w]
+        groups.append({"n": w, "n_states": len(sel), "gates": g, "params": thetas[sel], "terms": H})
+        index.append(sel)
+    t0 = time.perf_counter()
+    b = qsim.Batch(groups, dtype="complex64", use_graph=True)
+    create_s = time.perf_counter() - t0
+    b.qsim_batch_run()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        b.qsim_batch_run()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ev = np.zeros(n_circuits)
+    for gi, sel in enumerate(index):
+        ev[sel] = b.qsim_batch_results(gi)["expvals"]
+    info = b.qsim_batch_info()
+    b.close()
+    best = min(times)
+    # one circuit at a time, complex128: compile (bind angles on host, fuse,
+    # plan), run, <H>
+    rng = np.random.default_rng(11)
+    pick = rng.choice(n_circuits, size=min(sample_one_at_a_time, n_circuits), replace=False)
+    diffs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in pick:
+        w = int(widths[c])
+        g, H = tmpl[w]
+        sv = qsim.StateVector(w, "complex128")
+        sv.qsim_apply(g, params=thetas[c])
+        e = sv.qsim_expval(H)
+        diffs.append(abs(e - ev[c]) / np.abs(H["coeff"]).sum())
+        sv.close()
+    torch.cuda.synchronize()
+    one_s = (time.perf_counter() - t0) / len(pick)
+    return {"workload": f"{n_circuits} circuits, widths U{{10..20}}, {n_exp} exponentials each, own angles, "
+                        "complex64 + FP64 <H>, one HIP-graph launch",
+            "circuits_per_s": n_circuits / best, "seconds": best, "create_s": create_s,
+            "state_bytes": info["state_bytes"], "passes": info["passes"],
+            "one_at_a_time_c128_circuits_per_s": 1.0 / one_s,
+            "speedup_vs_one_at_a_time_c128": (n_circuits / best) * one_s,
+            "max_rel_dexpval_vs_c128": float(max(diffs))}
+
+
+def run_served(qsim, W, n_requests=48, load=0.8, wmax=30):
+    """Serving form: requests with log-uniform widths 12..wmax and depths
+    10^3..10^5 gates of the Pauli-exponential style, complex64; first all at
+    once (capacity), then Poisson arrivals at `load` x capacity."""
+    import numpy as np
+    reqs = W.serving_requests(2 * n_requests, 12, wmax, rate=1.0, seed=8)
+    circuits = [(r["width"], W.request_circuit(r), W.pauli_sum(r["width"], 20, seed=r["seed"])) for r in reqs]
+
+    def serve(batch, arrivals):
+        srv = qsim.Server(dtype="complex64", slots=8, compile_threads=8, pool_bytes=48 << 30)
+        t0 = srv.qsim_server_clock()
+        ids = {}
+        done = {}
+        for (w, g, H), a in zip(batch, arrivals):
+            while srv.qsim_server_clock() < t0 + a:
+                for r in srv.qsim_server_poll(wait_ms=0):
+                    done[r["id"]] = r
+                time.sleep(0.0005)
+            ids[srv.qsim_server_submit(w, g, terms=H)] = w
+        while len(done) < len(ids):
+            for r in srv.qsim_server_poll(wait_ms=100):
+                done[r["id"]] = r
+        st = srv.qsim_server_stats()
+        srv.close()
+        lat = [r["t_done"] - r["t_submit"] for r in done.values()]
+        span = max(r["t_done"] for r in done.values()) - t0
+        bad = sum(1 for r in done.values() if r["status"] != 0)
+        return {"circuits_per_s": len(done) / span, "p50_s": pct(lat, 50), "p99_s": pct(lat, 99),
+                "failed": bad, "pool_peak_bytes": st["pool_peak"]}
+
+    cap = serve(circuits[:n_requests], [0.0] * n_requests)
+    rate = load * cap["circuits_per_s"]
+    gaps = np.random.default_rng(9).exponential(1.0 / rate, size=n_requests)
+    pois = serve(circuits[n_requests:], list(np.cumsum(gaps)))
+    widths = [c[0] for c in circuits]
+    depths = [len(c[1]) for c in circuits]
+    return {"workload": f"{2 * n_requests} requests, widths log-U[12,{wmax}] (max {max(widths)}), depths "
+                        f"{min(depths)}..{max(depths)} gates, complex64, 8 slots, HBM-byte admission",
+            "capacity": cap, "poisson": dict(pois, offered_per_s=rate)}
+
+
+def run_wide_job(qsim, W, n=30, n_exp=8000):
+    """One 30-qubit complex64 job (8 GiB state, HBM-bound passes)."""
+    import torch
+    g, _, _ = W.pauli_exponential_circuit(n, n_exp, seed=31)
+    prog = qsim.Program(n, g, "complex64")
+    st = prog.qsim_program_stats()
+    sv = qsim.StateVector(n, "complex64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prog.qsim_run_timed(sv)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms, launches = prog.qsim_program_kernel_ms()
+    nrm = sv.qsim_norm()
+    prog.close()
+    sv.close()
+    pass_bytes = 2 * 8 * (1 << n)
+    gbs = pass_bytes / (ms * 1e-3 / launches) / 1e9
+    return {"workload": f"{n} qubits, {n_exp} exponentials ({st['input_gates']} gates), complex64",
+            "passes": st["passes"], "seconds": dt, "gates_per_s": st["input_gates"] / dt,
+            "avg_pass_ms": ms / launches, "pass_GBps": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+            "norm": nrm}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +216,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the passes as a HIP graph")
     ap.add_argument("--also", action="store_true", help="also measure the other dtype")
+    ap.add_argument("--forms", default="", help="comma list of extra forms to run: "
+                    "trajectories,batched,served,wide (or 'all')")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); "
@@ -127,6 +284,16 @@ def main():
         return res
 
     main_res = measure(args.dtype)
+    forms = {}
+    want = set(args.forms.split(",")) if args.forms else set()
+    if "all" in want:
+        want = {"trajectories", "batched", "served", "wide"}
+    for name, fn in (("trajectories", run_trajectories), ("batched", run_batched),
+                     ("served", run_served), ("wide", run_wide_job)):
+        if name in want:
+            log(f"[bench] form: {name}")
+            forms[name] = fn(qsim, W)
+            log(f"[bench] {name}: {json.dumps(forms[name])}")
     other = None
     if args.also:
         other = measure("complex64" if args.dtype == "complex128" else "complex128")
@@ -163,6 +330,8 @@ def main():
     if "kernel_ms_per_step" in main_res:
         out["kernel_ms_per_step"] = main_res["kernel_ms_per_step"]
         out["avg_pass_us"] = main_res["avg_pass_us"]
+    if forms:
+        out["forms"] = forms
     if other is not None:
         out["other_dtype"] = {k: other[k] for k in ("dtype", "ms_per_step", "gates_per_s", "energy")}
         if "roofline" in other:

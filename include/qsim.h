@@ -277,6 +277,69 @@ int qsim_batch_get_state(qsim_batch_h b, int group, int index, void *host_dst);
 int qsim_batch_info_get(qsim_batch_h b, qsim_batch_info *out);
 int qsim_batch_destroy(qsim_batch_h b);
 
+/* ----------------------------------------------------------- serving */
+
+/* A request loop with continuous batching: requests (circuits of any width)
+ * are compiled by host worker threads as they arrive and admitted, in
+ * arrival order, as soon as a slot (a HIP stream) and enough pool memory
+ * (2^n state elements) are free; admitted requests run concurrently on the
+ * device.  Each request's plan and kernels do not depend on what else is
+ * resident, so its result is the same alone and in any mix.  The server
+ * owns one device pool, allocated at creation. */
+typedef struct qsim_server *qsim_server_h;
+
+typedef struct qsim_server_opts {
+    int32_t dtype;            /* QSIM_C64 or QSIM_C128 */
+    int32_t slots;            /* requests resident at once (streams), 1..64 */
+    int32_t compile_threads;  /* host compile workers, 1..64 */
+    int32_t pad;
+    size_t pool_bytes;        /* device pool for states (admission budget) */
+    qsim_fuse_opts fuse;      /* level 0 selects the default */
+} qsim_server_opts;
+
+typedef struct qsim_request {
+    int32_t n;                /* width */
+    int32_t pad;
+    const qsim_gate *g;       /* copied at submit */
+    size_t ng;
+    const double *mats;       /* MAT pool, copied; `n_mats` complex entries */
+    size_t n_mats;
+    const qsim_pauli *terms;  /* observable, copied; may be NULL */
+    size_t n_terms;
+    void *host_state_out;     /* if not NULL, receives the final state (2^n
+                                 elements) before the result is reported; the
+                                 caller keeps it valid until then */
+} qsim_request;
+
+typedef struct qsim_result {
+    int64_t id;
+    int32_t status;           /* QSIM_OK or the request's error */
+    int32_t n;
+    double expval;            /* <H>/<psi|psi> (0 without terms) */
+    double norm;              /* <psi|psi> */
+    double t_submit, t_admit, t_done;   /* seconds, server clock (qsim_server_clock) */
+    int64_t passes;
+} qsim_result;
+
+typedef struct qsim_server_stats {
+    int64_t submitted, completed, rejected, in_flight, waiting;
+    size_t pool_bytes, pool_in_use, pool_peak;
+} qsim_server_stats;
+
+/* Errors: QSIM_E_ARG, QSIM_E_NOMEM (pool allocation), QSIM_E_HIP. */
+int qsim_server_create(const qsim_server_opts *opt, qsim_server_h *out);
+/* Copy the request and queue it; writes its id.  QSIM_E_CAPACITY if the
+ * state can never fit the pool, QSIM_E_ARG for a bad width or list. */
+int qsim_server_submit(qsim_server_h s, const qsim_request *r, int64_t *id);
+/* Move up to `max` finished results into `out`; writes how many.  With
+ * wait_ms > 0, blocks up to that long for at least one. */
+int qsim_server_poll(qsim_server_h s, qsim_result *out, int max, int *n_out, int wait_ms);
+int qsim_server_get_stats(qsim_server_h s, qsim_server_stats *out);
+/* Seconds on the server clock (steady clock), for arrival bookkeeping. */
+double qsim_server_clock(void);
+/* Finish everything in flight, then free the server. */
+int qsim_server_destroy(qsim_server_h s);
+
 /* ------------------------------------------------------- host-only tools */
 
 /* Run lowering and fusion only (no device): writes the fused operators as

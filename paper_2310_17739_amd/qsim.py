@@ -98,20 +98,20 @@ def _load():
 
 
 def _bind_optional(lib):
-    """Entry points of the served form (declared in qsim.h)."""
+    """Entry points of the served form."""
     P, I, SZ, D = C.c_void_p, C.c_int, C.c_size_t, C.c_double
     opt = {
         "qsim_server_create": ([P, P], I),
         "qsim_server_submit": ([P, P, P], I),
-        "qsim_server_poll": ([P, P, I, P], I),
-        "qsim_server_stats": ([P, P], I),
+        "qsim_server_poll": ([P, P, I, P, I], I),
+        "qsim_server_get_stats": ([P, P], I),
+        "qsim_server_clock": ([], D),
         "qsim_server_destroy": ([P], I),
     }
     for name, (args, res) in opt.items():
-        if hasattr(lib, name):
-            f = getattr(lib, name)
-            f.argtypes = args
-            f.restype = res
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
 
 
 class qsim_batch_group(C.Structure):
@@ -386,6 +386,104 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             _lib.qsim_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class qsim_server_opts(C.Structure):
+    _fields_ = [("dtype", C.c_int32), ("slots", C.c_int32), ("compile_threads", C.c_int32),
+                ("pad", C.c_int32), ("pool_bytes", C.c_size_t), ("fuse", qsim_fuse_opts)]
+
+
+class qsim_request(C.Structure):
+    _fields_ = [("n", C.c_int32), ("pad", C.c_int32), ("g", C.c_void_p), ("ng", C.c_size_t),
+                ("mats", C.c_void_p), ("n_mats", C.c_size_t), ("terms", C.c_void_p),
+                ("n_terms", C.c_size_t), ("host_state_out", C.c_void_p)]
+
+
+class qsim_result(C.Structure):
+    _fields_ = [("id", C.c_int64), ("status", C.c_int32), ("n", C.c_int32), ("expval", C.c_double),
+                ("norm", C.c_double), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double), ("passes", C.c_int64)]
+
+
+class qsim_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
+                ("in_flight", C.c_int64), ("waiting", C.c_int64), ("pool_bytes", C.c_size_t),
+                ("pool_in_use", C.c_size_t), ("pool_peak", C.c_size_t)]
+
+
+class Server:
+    """The serving form (qsim_server_*): submit circuits, poll results."""
+
+    def __init__(self, dtype="complex64", slots=8, compile_threads=4, pool_bytes=8 << 30,
+                 level=None, max_width=None, tile_qubits=None, flags=0):
+        o = qsim_server_opts()
+        o.dtype = QSIM_DTYPES[dtype]
+        o.slots = int(slots)
+        o.compile_threads = int(compile_threads)
+        o.pool_bytes = int(pool_bytes)
+        fo = _opts(level, max_width, tile_qubits, flags)
+        if fo is not None:
+            o.fuse = fo
+        self.dtype = o.dtype
+        h = C.c_void_p()
+        check(_lib.qsim_server_create(C.byref(o), C.byref(h)), "qsim_server_create")
+        self.h = h
+        self._keep = {}
+
+    def qsim_server_submit(self, n, gates, terms=None, mats=None, want_state=False) -> int:
+        g = np.ascontiguousarray(gates, dtype=GATE_DTYPE)
+        t = None if terms is None else np.ascontiguousarray(terms, dtype=PAULI_DTYPE)
+        m = None if mats is None else np.ascontiguousarray(mats, dtype=np.complex128)
+        out = None
+        if want_state:
+            out = np.empty(1 << n, dtype=np.complex64 if self.dtype == C64 else np.complex128)
+        r = qsim_request()
+        r.n = int(n)
+        r.g = g.ctypes.data
+        r.ng = len(g)
+        r.mats = None if m is None else m.ctypes.data
+        r.n_mats = 0 if m is None else len(m)
+        r.terms = None if t is None else t.ctypes.data
+        r.n_terms = 0 if t is None else len(t)
+        r.host_state_out = None if out is None else out.ctypes.data
+        rid = C.c_int64()
+        check(_lib.qsim_server_submit(self.h, C.byref(r), C.byref(rid)), "qsim_server_submit")
+        if out is not None:
+            self._keep[rid.value] = out
+        return rid.value
+
+    def qsim_server_poll(self, max_results=256, wait_ms=0):
+        arr = (qsim_result * max_results)()
+        k = C.c_int()
+        check(_lib.qsim_server_poll(self.h, arr, max_results, C.byref(k), int(wait_ms)), "qsim_server_poll")
+        res = []
+        for i in range(k.value):
+            a = arr[i]
+            d = {f: getattr(a, f) for f, _ in qsim_result._fields_}
+            if a.id in self._keep:
+                d["state"] = self._keep.pop(a.id)
+            res.append(d)
+        return res
+
+    def qsim_server_stats(self) -> dict:
+        st = qsim_server_stats()
+        check(_lib.qsim_server_get_stats(self.h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in qsim_server_stats._fields_}
+
+    @staticmethod
+    def qsim_server_clock() -> float:
+        return _lib.qsim_server_clock()
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.qsim_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

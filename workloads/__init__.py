@@ -85,18 +85,39 @@ assert PAULI_DTYPE.itemsize == 24
 
 def gates(records) -> np.ndarray:
     """Build a gate array from tuples ``(kind, qubits, thetas[, slot])``."""
-    out = np.zeros(len(records), dtype=GATE_DTYPE)
+    n = len(records)
+    out = np.zeros(n, dtype=GATE_DTYPE)
+    if n == 0:
+        return out
+    kinds = np.empty(n, dtype=np.uint16)
+    nq = np.empty(n, dtype=np.uint16)
+    q = np.zeros((n, 5), dtype=np.int32)
+    th = np.zeros((n, 3), dtype=np.float64)
+    slot = np.full(n, -1, dtype=np.int32)
     for i, rec in enumerate(records):
-        kind, qs = rec[0], rec[1]
-        th = rec[2] if len(rec) > 2 else ()
-        slot = rec[3] if len(rec) > 3 else -1
-        qs = list(qs) if np.iterable(qs) else [int(qs)]
-        out[i]["kind"] = kind
-        out[i]["nq"] = len(qs)
-        out[i]["q"][: len(qs)] = qs
-        th = list(th) if np.iterable(th) else [float(th)]
-        out[i]["theta"][: len(th)] = th
-        out[i]["slot"] = slot
+        kinds[i] = rec[0]
+        qs = rec[1]
+        if np.iterable(qs):
+            k = len(qs)
+            q[i, :k] = qs
+        else:
+            k = 1
+            q[i, 0] = qs
+        nq[i] = k
+        if len(rec) > 2:
+            t = rec[2]
+            if np.iterable(t):
+                if len(t):
+                    th[i, :len(t)] = t
+            else:
+                th[i, 0] = t
+        if len(rec) > 3:
+            slot[i] = rec[3]
+    out["kind"] = kinds
+    out["nq"] = nq
+    out["q"] = q
+    out["theta"] = th
+    out["slot"] = slot
     return out
 
 
@@ -151,14 +172,17 @@ def random_all_kinds(n: int, n_gates: int, seed: int,
 def pauli_strings(n: int, count: int, rng: np.random.Generator,
                   wmin: int = 2, wmax: int = 4):
     """``count`` random Pauli strings: weight U{wmin..wmax}, qubits drawn
-    without replacement, letters U{X, Y, Z}.  Returns a list of
-    (sorted qubit array, letter array) with letters 1=X, 2=Y, 3=Z."""
+    without replacement (the first w of a random permutation), letters
+    U{X, Y, Z}.  Returns a list of (sorted qubit array, letter array) with
+    letters 1=X, 2=Y, 3=Z."""
+    wmax = min(wmax, n)
+    ws = rng.integers(wmin, wmax + 1, size=count)
+    perm = np.argsort(rng.random((count, n)), axis=1)[:, :wmax]
+    lets = rng.integers(1, 4, size=(count, wmax))
     out = []
-    for _ in range(count):
-        w = int(rng.integers(wmin, wmax + 1))
-        qs = np.sort(rng.choice(n, size=w, replace=False))
-        letters = rng.integers(1, 4, size=w)
-        out.append((qs, letters))
+    for i in range(count):
+        w = int(ws[i])
+        out.append((np.sort(perm[i, :w]), lets[i, :w].copy()))
     return out
 
 
