@@ -62,6 +62,10 @@ void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc
     if (dtype == QSIM_C128) fc->max_width = std::min(fc->max_width, 4);
     fc->max_width = std::max(1, std::min(fc->max_width, kMaxK));
     fc->lds_cost = pc->one_op_per_pass ? 64.0 : 3.0;
+    if (const char *v = std::getenv("QSIM_LDS_COST")) fc->lds_cost = std::atof(v);
+    if (!opt || opt->max_width <= 0) fc->max_width = env_int("QSIM_MAX_WIDTH", fc->max_width);
+    if (dtype == QSIM_C128) fc->max_width = std::min(fc->max_width, 4);
+    fc->max_width = std::max(1, std::min(fc->max_width, kMaxK));
     pc->tile_qubits = std::max(6, std::min(pc->tile_qubits, resident_max(dtype)));
     if (n <= resident_max(dtype)) pc->tile_qubits = n;
     if (pc->tile_qubits > n) pc->tile_qubits = n;

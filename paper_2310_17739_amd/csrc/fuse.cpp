@@ -132,32 +132,46 @@ void mul_small(Op *big, const Op &small, bool left) {
     const size_t BB = size_t(D) * D, sb = size_t(d) * d;
     const int nb_big = 1 << big->np, nb_small = 1 << small.np;
     std::vector<cd> res(BB * nb_big * nb_small);
-    cd v[1 << kMaxK];
+    // the small factor's nonzero entries, as (row, col, re, im); complex
+    // products are written out (std::complex's operator* takes the
+    // NaN-checking library path)
+    struct Nz { int i, j; double re, im; };
     for (int bs = 0; bs < nb_small; bs++) {
         const cd *S = small.m.data() + bs * sb;
+        Nz nz[(1 << kMaxK) * (1 << kMaxK)];
+        int nnz = 0;
+        for (int i = 0; i < d; i++)
+            for (int j = 0; j < d; j++) {
+                const cd v = S[size_t(i) * d + j];
+                if (v.real() != 0.0 || v.imag() != 0.0) nz[nnz++] = {i, j, v.real(), v.imag()};
+            }
         for (int bb = 0; bb < nb_big; bb++) {
-            const cd *M = big->m.data() + bb * BB;
-            cd *R = res.data() + (size_t(bb) + size_t(bs) * nb_big) * BB;
+            const double *M = reinterpret_cast<const double *>(big->m.data() + bb * BB);
+            double *R = reinterpret_cast<double *>(res.data() + (size_t(bb) + size_t(bs) * nb_big) * BB);
             for (int g = 0; g < (D >> small.k); g++) {
-                int base = insert_zeros(g, pos, small.k);
+                const int base = insert_zeros(g, pos, small.k);
                 if (left) {
-                    // rows of the group mix: R[base+off[i]][c] = sum_j S[i][j] M[base+off[j]][c]
-                    for (int c = 0; c < D; c++) {
-                        for (int j = 0; j < d; j++) v[j] = M[size_t(base + off[j]) * D + c];
-                        for (int i = 0; i < d; i++) {
-                            cd acc = 0;
-                            for (int j = 0; j < d; j++) acc += S[size_t(i) * d + j] * v[j];
-                            R[size_t(base + off[i]) * D + c] = acc;
+                    // R[base+off[i]][c] = sum_j S[i][j] M[base+off[j]][c]
+                    for (int e = 0; e < nnz; e++) {
+                        const double *src = M + 2 * size_t(base + off[nz[e].j]) * D;
+                        double *dst = R + 2 * size_t(base + off[nz[e].i]) * D;
+                        const double sr = nz[e].re, si = nz[e].im;
+                        for (int c = 0; c < D; c++) {
+                            const double mr = src[2 * c], mi = src[2 * c + 1];
+                            dst[2 * c] += sr * mr - si * mi;
+                            dst[2 * c + 1] += sr * mi + si * mr;
                         }
                     }
                 } else {
-                    // columns mix: R[r][base+off[i]] = sum_j M[r][base+off[j]] S[j][i]
+                    // R[r][base+off[i]] = sum_j M[r][base+off[j]] S[j][i]
                     for (int r = 0; r < D; r++) {
-                        for (int j = 0; j < d; j++) v[j] = M[size_t(r) * D + base + off[j]];
-                        for (int i = 0; i < d; i++) {
-                            cd acc = 0;
-                            for (int j = 0; j < d; j++) acc += v[j] * S[size_t(j) * d + i];
-                            R[size_t(r) * D + base + off[i]] = acc;
+                        const double *src = M + 2 * size_t(r) * D;
+                        double *dst = R + 2 * size_t(r) * D;
+                        for (int e = 0; e < nnz; e++) {
+                            const double mr = src[2 * (base + off[nz[e].i])], mi = src[2 * (base + off[nz[e].i]) + 1];
+                            const double sr = nz[e].re, si = nz[e].im;
+                            dst[2 * (base + off[nz[e].j])] += mr * sr - mi * si;
+                            dst[2 * (base + off[nz[e].j]) + 1] += mr * si + mi * sr;
                         }
                     }
                 }
