@@ -111,6 +111,10 @@ typedef struct qsim_fuse_opts {
     int32_t max_width;   /* 2..5 (complex128 is limited to 4); 0 = default */
     int32_t tile_qubits; /* qubits per LDS tile; 0 = default for n and dtype */
     int32_t flags;       /* QSIM_F_* */
+    float op_cost;       /* fusion cost of one more operator, in complex MACs
+                            per amplitude; 0 = default (3) */
+    int32_t low_qubits;  /* contiguous low qubits in every tile; 0 = default
+                            (4 for complex64, 3 for complex128) */
 } qsim_fuse_opts;
 
 enum {
@@ -339,6 +343,28 @@ int qsim_server_get_stats(qsim_server_h s, qsim_server_stats *out);
 double qsim_server_clock(void);
 /* Finish everything in flight, then free the server. */
 int qsim_server_destroy(qsim_server_h s);
+
+/* ----------------------------------------------------------- sampling */
+
+/* Draw m shots of all n qubits at once from the current state (Section
+ * 4.3: after measurement assertion the final state is sampled for all m
+ * shots together).  Shot s is the smallest basis index x with
+ * C(x) > u[s] * C(2^n - 1), where C is the FP64 inclusive prefix sum of
+ * |a_x|^2 in index order; u[s] in [0,1).  out[s] receives x.  Synchronous;
+ * uses 8 * 2^n bytes of device scratch, allocated on first use. */
+int qsim_sample(qsim_h h, const double *uniforms, size_t m, uint64_t *out);
+
+/* ----------------------------------------------------------- autotune */
+
+/* Pick fusion width, per-operator cost, tile qubits and contiguous low
+ * qubits for this circuit on this device: each candidate compiles a prefix
+ * of the circuit (up to `prefix_gates` records, 0 = 20000) and runs it on
+ * h's state, timed with HIP events; the fastest per input gate wins.  The
+ * state is left as |0...0>.  Writes the chosen options (level 5) and their
+ * time per input gate in ns.  Synchronous. */
+int qsim_autotune(qsim_h h, const qsim_gate *g, size_t ng, const double *mats,
+                  const double *params, size_t prefix_gates, qsim_fuse_opts *best,
+                  double *ns_per_gate);
 
 /* ------------------------------------------------------- host-only tools */
 

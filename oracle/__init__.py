@@ -166,6 +166,15 @@ def expval(n, psi, terms) -> float:
     return _load().orc_expval(n, _ptr(np.ascontiguousarray(psi, dtype=np.complex128)), _ptr(t), len(t))
 
 
+def sample(n, psi, uniforms) -> np.ndarray:
+    """m shots of all qubits at once from psi (Section 4.3, sampling after
+    measurement assertion): shot s is the smallest x with C(x) > u_s C(2^n-1),
+    C the inclusive cumulative sum of |psi_x|^2 in index order."""
+    w = np.abs(np.asarray(psi, dtype=np.complex128)) ** 2
+    c = np.cumsum(w)
+    return np.searchsorted(c, np.asarray(uniforms) * c[-1], side="right").astype(np.uint64)
+
+
 def infidelity(a, b) -> float:
     """1 - |<a|b>|^2 / (<a|a><b|b>), evaluated in extended precision where
     available so that values near 1e-16 are meaningful."""

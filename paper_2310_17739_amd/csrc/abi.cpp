@@ -56,6 +56,7 @@ void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc
         if (opt->level >= 0 && opt->level <= 5) fc->level = opt->level;
         if (opt->max_width > 0) fc->max_width = opt->max_width;
         if (opt->tile_qubits > 0) pc->tile_qubits = opt->tile_qubits;
+        if (opt->low_qubits > 0) pc->low_qubits = opt->low_qubits;
         pc->one_op_per_pass = (opt->flags & QSIM_F_ONE_OP_PER_PASS) != 0;
         fc->sparse = (opt->flags & QSIM_F_NO_SPARSE) == 0;
     }
@@ -63,6 +64,7 @@ void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc
     fc->max_width = std::max(1, std::min(fc->max_width, kMaxK));
     fc->lds_cost = pc->one_op_per_pass ? 64.0 : 3.0;
     if (const char *v = std::getenv("QSIM_LDS_COST")) fc->lds_cost = std::atof(v);
+    if (opt && opt->op_cost > 0.0f) fc->lds_cost = opt->op_cost;
     if (!opt || opt->max_width <= 0) fc->max_width = env_int("QSIM_MAX_WIDTH", fc->max_width);
     if (dtype == QSIM_C128) fc->max_width = std::min(fc->max_width, 4);
     fc->max_width = std::max(1, std::min(fc->max_width, kMaxK));
@@ -329,6 +331,8 @@ struct qsim_state {
     size_t cap_small = 0;
     void *d_masks = nullptr;   // Pauli masks of qsim_expval
     size_t cap_masks = 0;
+    void *d_scan = nullptr;    // sampling: prefix sums, block sums, shots
+    size_t cap_scan = 0;
     double *h_out = nullptr;   // pinned readback
     size_t cap_out = 0;
     qsim_apply_stats last{};
@@ -447,6 +451,7 @@ int qsim_destroy(qsim_h h) {
     if (h->d_red) hipFree(h->d_red);
     if (h->d_small) hipFree(h->d_small);
     if (h->d_masks) hipFree(h->d_masks);
+    if (h->d_scan) hipFree(h->d_scan);
     if (h->h_out) hipHostFree(h->h_out);
     delete h;
     return QSIM_OK;
@@ -728,6 +733,36 @@ int qsim_expval(qsim_h h, const qsim_pauli *t, size_t nt, double *out) {
     return QSIM_OK;
 }
 
+int qsim_sample(qsim_h h, const double *u, size_t m, uint64_t *out) {
+    if (!h || (m && (!u || !out))) return QSIM_E_ARG;
+    for (size_t s = 0; s < m; s++)
+        if (!(u[s] >= 0.0 && u[s] < 1.0)) return QSIM_E_ARG;
+    const uint64_t len = uint64_t(1) << h->n;
+    const uint64_t nb = qk::scan_blocks(h->n);
+    // layout: cum[len] | bsum[nb] | boff[nb] | u[m] | shots[m]
+    const size_t need = (len + 2 * nb + 2 * m) * 8 + 1024;
+    int rc = grow(&h->d_scan, &h->cap_scan, need, h->stream);
+    if (rc) return rc;
+    double *cum = (double *)h->d_scan, *bsum = cum + len, *boff = bsum + nb, *du = boff + nb;
+    uint64_t *dshot = (uint64_t *)(du + m);
+    if ((rc = qk::launch_blockscan(h->dtype, h->buf, h->n, cum, bsum, h->stream))) return rc;
+    std::vector<double> bs(nb);
+    if ((rc = hip_rc(hipMemcpyAsync(bs.data(), bsum, nb * 8, hipMemcpyDeviceToHost, h->stream)))) return rc;
+    if ((rc = hip_rc(hipStreamSynchronize(h->stream)))) return rc;
+    double acc = 0.0;
+    for (uint64_t b = 0; b < nb; b++) {   // exclusive prefix of block totals, in order
+        const double v = bs[b];
+        bs[b] = acc;
+        acc += v;
+    }
+    if (!(acc > 0.0)) return QSIM_E_ZERO_PROB;
+    if ((rc = hip_rc(hipMemcpyAsync(boff, bs.data(), nb * 8, hipMemcpyHostToDevice, h->stream)))) return rc;
+    if (m && (rc = hip_rc(hipMemcpyAsync(du, u, m * 8, hipMemcpyHostToDevice, h->stream)))) return rc;
+    if ((rc = qk::launch_addoff_search(cum, h->n, boff, du, m, dshot, h->stream))) return rc;
+    if (m && (rc = hip_rc(hipMemcpyAsync(out, dshot, m * 8, hipMemcpyDeviceToHost, h->stream)))) return rc;
+    return hip_rc(hipStreamSynchronize(h->stream));
+}
+
 int qsim_get_state(qsim_h h, void *dst) {
     if (!h || !dst) return QSIM_E_ARG;
     size_t bytes = (size_t(1) << h->n) * elem_bytes(h->dtype);
@@ -740,6 +775,68 @@ int qsim_set_state(qsim_h h, const void *src) {
     size_t bytes = (size_t(1) << h->n) * elem_bytes(h->dtype);
     if (hipMemcpyAsync(h->buf, src, bytes, hipMemcpyHostToDevice, h->stream) != hipSuccess) return QSIM_E_HIP;
     return hip_rc(hipStreamSynchronize(h->stream));
+}
+
+int qsim_autotune(qsim_h h, const qsim_gate *g, size_t ng, const double *mats, const double *params,
+                  size_t prefix_gates, qsim_fuse_opts *best, double *ns_per_gate) {
+    if (!h || !best || (ng && !g)) return QSIM_E_ARG;
+    if (prefix_gates == 0) prefix_gates = 20000;
+    // the prefix ends at a whole number of records; barriers are kept
+    const size_t np = std::min(ng, prefix_gates);
+    std::vector<qsim_fuse_opts> cands;
+    const int tdef = h->dtype == QSIM_C64 ? 13 : 12;
+    const int ldef = h->dtype == QSIM_C64 ? 4 : 3;
+    const int wmax = h->dtype == QSIM_C64 ? 5 : 4;
+    for (int t : {tdef - 1, tdef, tdef + 1}) {
+        if (t > resident_max(h->dtype)) continue;
+        for (int w = 3; w <= wmax; w++)
+            for (float cost : {2.0f, 4.0f, 8.0f})
+                for (int low : {ldef - 1, ldef}) {
+                    qsim_fuse_opts o{};
+                    o.level = 5;
+                    o.max_width = w;
+                    o.tile_qubits = t;
+                    o.op_cost = cost;
+                    o.low_qubits = low;
+                    cands.push_back(o);
+                }
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return QSIM_E_HIP;
+    double best_ns = 1e300;
+    int rc = QSIM_OK;
+    DeviceTables dt;
+    for (const qsim_fuse_opts &o : cands) {
+        Compiled c;
+        try {
+            rc = compile_circuit(h->n, h->dtype, g, np, mats, params, &o, &c);
+        } catch (const std::bad_alloc &) {
+            rc = QSIM_E_NOMEM;
+        }
+        if (rc) break;
+        if (c.plan.ops.empty()) continue;
+        if ((rc = upload_plan(&dt, h->dtype, c.plan, h->stream))) break;
+        // warm, then time one run
+        if ((rc = enqueue_passes(c, dt, h->dtype, h->buf, h->stream, false))) break;
+        hipEventRecord(e0, h->stream);
+        if ((rc = enqueue_passes(c, dt, h->dtype, h->buf, h->stream, false))) break;
+        hipEventRecord(e1, h->stream);
+        if ((rc = hip_rc(hipEventSynchronize(e1)))) break;
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        const double ns = 1e6 * double(ms) / double(std::max<int64_t>(1, c.stats.input_gates));
+        if (ns < best_ns) {
+            best_ns = ns;
+            *best = o;
+        }
+    }
+    free_tables(&dt);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (!rc) rc = qk::launch_init_zero(h->dtype, h->buf, 0, 1, h->n, h->stream);
+    if (!rc) rc = hip_rc(hipStreamSynchronize(h->stream));
+    if (ns_per_gate) *ns_per_gate = best_ns;
+    return rc;
 }
 
 int qsim_debug_fuse(int n, const qsim_gate *g, size_t ng, const double *mats, const double *params,

@@ -572,6 +572,68 @@ __global__ void __launch_bounds__(NT) k_fill_i32(int32_t *__restrict__ p, int32_
     for (uint64_t i = uint64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += uint64_t(gridDim.x) * NT) p[i] = v;
 }
 
+// -------------------------------------------------------------- sampling
+// Inclusive prefix sums of |a_x|^2 in FP64, in three fixed-order steps:
+// per-block local scans (4096 elements per block, 16 per thread), block
+// totals scanned on the host, block offsets added back.
+constexpr int SCAN_PER_THREAD = 16;
+constexpr int SCAN_BLOCK = NT * SCAN_PER_THREAD;
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_blockscan(const Cx<T> *__restrict__ state, uint64_t len,
+                                                  double *__restrict__ cum, double *__restrict__ bsum) {
+    __shared__ double tsum[NT];
+    const uint64_t b0 = uint64_t(blockIdx.x) * SCAN_BLOCK + uint64_t(threadIdx.x) * SCAN_PER_THREAD;
+    double loc[SCAN_PER_THREAD];
+    double run = 0.0;
+#pragma unroll
+    for (int i = 0; i < SCAN_PER_THREAD; i++) {
+        const uint64_t x = b0 + i;
+        run += (x < len) ? norm2(state[x]) : 0.0;
+        loc[i] = run;
+    }
+    tsum[threadIdx.x] = run;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double acc = 0.0;
+        for (int j = 0; j < NT; j++) {
+            const double v = tsum[j];
+            tsum[j] = acc;    // exclusive prefix of thread totals
+            acc += v;
+        }
+        bsum[blockIdx.x] = acc;
+    }
+    __syncthreads();
+    const double off = tsum[threadIdx.x];
+#pragma unroll
+    for (int i = 0; i < SCAN_PER_THREAD; i++) {
+        const uint64_t x = b0 + i;
+        if (x < len) cum[x] = off + loc[i];
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_addoff(double *__restrict__ cum, uint64_t len,
+                                               const double *__restrict__ boff) {
+    for (uint64_t x = uint64_t(blockIdx.x) * NT + threadIdx.x; x < len; x += uint64_t(gridDim.x) * NT)
+        cum[x] += boff[x / SCAN_BLOCK];
+}
+
+// Shot s: smallest x with cum[x] > u[s] * cum[len - 1].
+__global__ void __launch_bounds__(NT) k_search(const double *__restrict__ cum, uint64_t len,
+                                               const double *__restrict__ u, uint64_t m,
+                                               uint64_t *__restrict__ out) {
+    const uint64_t s = uint64_t(blockIdx.x) * NT + threadIdx.x;
+    if (s >= m) return;
+    const double target = u[s] * cum[len - 1];
+    uint64_t lo = 0, hi = len - 1;
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (cum[mid] > target) hi = mid;
+        else lo = mid + 1;
+    }
+    out[s] = lo;
+}
+
 // ------------------------------------------------------------- launchers
 namespace {
 int check(hipError_t e) { return note_hip(e, "kernel launch"); }
@@ -780,6 +842,26 @@ int launch_bind(int dtype, const double *tmpl, const BindEntry *ents, uint32_t n
 int launch_fill_i32(int32_t *p, int32_t v, uint64_t n, hipStream_t st) {
     if (n == 0) return QSIM_OK;
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(NT), 0, st, p, v, n);
+    return check(hipGetLastError());
+}
+
+uint64_t scan_blocks(int n) { return ((uint64_t(1) << n) + SCAN_BLOCK - 1) / SCAN_BLOCK; }
+
+int launch_blockscan(int dtype, const void *state, int n, double *cum, double *bsum, hipStream_t st) {
+    const uint64_t len = uint64_t(1) << n;
+    const dim3 grid(uint32_t(scan_blocks(n)));
+    if (dtype == QSIM_C64)
+        hipLaunchKernelGGL(k_blockscan<float>, grid, dim3(NT), 0, st, (const Cx<float> *)state, len, cum, bsum);
+    else
+        hipLaunchKernelGGL(k_blockscan<double>, grid, dim3(NT), 0, st, (const Cx<double> *)state, len, cum, bsum);
+    return check(hipGetLastError());
+}
+
+int launch_addoff_search(double *cum, int n, const double *boff, const double *u, uint64_t m,
+                         uint64_t *out, hipStream_t st) {
+    const uint64_t len = uint64_t(1) << n;
+    hipLaunchKernelGGL(k_addoff, dim3(grid_for(len)), dim3(NT), 0, st, cum, len, boff);
+    if (m) hipLaunchKernelGGL(k_search, dim3(uint32_t((m + NT - 1) / NT)), dim3(NT), 0, st, cum, len, u, m, out);
     return check(hipGetLastError());
 }
 

@@ -82,6 +82,14 @@ int launch_bind(int dtype, const double *tmpl, const BindEntry *ents, uint32_t n
 
 int launch_fill_i32(int32_t *p, int32_t v, uint64_t n, hipStream_t st);
 
+// Sampling: per-block inclusive prefix sums of |a_x|^2 into cum[2^n] and
+// block totals into bsum[scan_blocks(n)]; then, with boff the exclusive
+// prefix of the block totals, finish the sums and search each shot.
+uint64_t scan_blocks(int n);
+int launch_blockscan(int dtype, const void *state, int n, double *cum, double *bsum, hipStream_t st);
+int launch_addoff_search(double *cum, int n, const double *boff, const double *u, uint64_t m,
+                         uint64_t *out, hipStream_t st);
+
 // |0...0> in every state of a batch.
 int launch_init_zero(int dtype, void *state, uint64_t sstride, uint32_t nstates, int n,
                      hipStream_t st);

@@ -35,7 +35,10 @@ class QsimError(RuntimeError):
 
 class qsim_fuse_opts(C.Structure):
     _fields_ = [("level", C.c_int32), ("max_width", C.c_int32), ("tile_qubits", C.c_int32),
-                ("flags", C.c_int32)]
+                ("flags", C.c_int32), ("op_cost", C.c_float), ("low_qubits", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class qsim_apply_stats(C.Structure):
@@ -82,6 +85,8 @@ def _load():
         "qsim_program_stats": ([P, P], I),
         "qsim_program_destroy": ([P], I),
         "qsim_debug_plan": ([I, I, P, SZ, P, P, P, P], I),
+        "qsim_autotune": ([P, P, SZ, P, P, SZ, P, P], I),
+        "qsim_sample": ([P, P, SZ, P], I),
         "qsim_batch_create": ([P, I, P, P], I),
         "qsim_batch_run": ([P, P], I),
         "qsim_batch_results": ([P, I, P, P, P, P, P], I),
@@ -148,14 +153,19 @@ def _p(a):
     return None if a is None else C.c_void_p(a.ctypes.data)
 
 
-def _opts(level=None, max_width=None, tile_qubits=None, flags=0):
-    if level is None and max_width is None and tile_qubits is None and not flags:
+def _opts(level=None, max_width=None, tile_qubits=None, flags=0, op_cost=None, low_qubits=None):
+    if isinstance(level, qsim_fuse_opts):
+        return level
+    if (level is None and max_width is None and tile_qubits is None and not flags and op_cost is None
+            and low_qubits is None):
         return None
     o = qsim_fuse_opts()
     o.level = 5 if level is None else int(level)
     o.max_width = int(max_width or 0)
     o.tile_qubits = int(tile_qubits or 0)
     o.flags = int(flags)
+    o.op_cost = float(op_cost or 0.0)
+    o.low_qubits = int(low_qubits or 0)
     return o
 
 
@@ -241,6 +251,24 @@ class StateVector:
         out = C.c_double()
         check(_lib.qsim_norm(self.h, C.byref(out)), "qsim_norm")
         return out.value
+
+    def qsim_autotune(self, gates, mats=None, params=None, prefix_gates=0):
+        """Returns (qsim_fuse_opts, ns per input gate) of the fastest candidate;
+        pass the options back as `level=` to qsim_apply / Program."""
+        g = np.ascontiguousarray(gates, dtype=GATE_DTYPE)
+        m = None if mats is None else np.ascontiguousarray(mats, dtype=np.complex128)
+        pr = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+        best = qsim_fuse_opts()
+        ns = C.c_double()
+        check(_lib.qsim_autotune(self.h, _p(g), len(g), _p(m), _p(pr), int(prefix_gates), C.byref(best),
+                                 C.byref(ns)), "qsim_autotune")
+        return best, ns.value
+
+    def qsim_sample(self, uniforms) -> np.ndarray:
+        u = np.ascontiguousarray(uniforms, dtype=np.float64)
+        out = np.zeros(len(u), dtype=np.uint64)
+        check(_lib.qsim_sample(self.h, _p(u), len(u), _p(out)), "qsim_sample")
+        return out
 
     def qsim_get_state(self) -> np.ndarray:
         out = np.empty(1 << self.n, dtype=np.complex64 if self.dtype == C64 else np.complex128)

@@ -231,3 +231,17 @@ def test_cfg2_full_circuit_inverse_property(Q, dtype):
         assert abs(nrm - 1) < 1e-9 and 1 - p0 < 1e-9
     else:
         assert abs(nrm - 1) < 1e-3 and 1 - p0 < 1e-4
+
+
+def test_autotune_picks_valid_options(Q):
+    n = 18
+    g, _, _ = W.pauli_exponential_circuit(n, 400, seed=21)
+    sv = Q.StateVector(n, "complex64")
+    best, ns = sv.qsim_autotune(g, prefix_gates=2000)
+    assert best.level == 5 and 3 <= best.max_width <= 5 and ns > 0
+    # state left at |0...0>, and the tuned options give the oracle's result
+    st = sv.qsim_get_state()
+    assert st[0] == 1 and np.count_nonzero(st) == 1
+    sv.qsim_apply(g, level=best)
+    want, _, _ = oracle.run(n, g)
+    check_state(sv.qsim_get_state(), want, "complex64")

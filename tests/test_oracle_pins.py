@@ -464,3 +464,25 @@ def test_norm_preserved_by_unitary_circuit():
     psi, _, _ = oracle.run(n, g)
     # each gate may move the norm by a few ulps (fl(1/sqrt 2) in H is not exact)
     assert abs(oracle.norm(n, psi) - 1) < 4.5e-16 * len(g)
+
+
+# ------------------------------------------------------------- sampling
+def test_sample_rule_on_known_distributions():
+    """m shots at once (Section 4.3): a basis state always gives its index;
+    on the uniform superposition the draw u = (x + 1/2)/2^n gives x; shot
+    frequencies of a skewed state pass a chi-square test."""
+    n = 5
+    basis = np.zeros(1 << n, complex)
+    basis[19] = 1
+    assert (oracle.sample(n, basis, W.uniforms(100, seed=1)) == 19).all()
+    uni, _, _ = oracle.run(n, W.gates([(W.KIND_H, (q,), ()) for q in range(n)]))
+    u = (np.arange(1 << n) + 0.5) / (1 << n)
+    assert np.array_equal(oracle.sample(n, uni, u), np.arange(1 << n))
+    psi, _, _ = oracle.run(n, W.random_circuit(n, 60, seed=3))
+    p = np.abs(psi) ** 2
+    shots = oracle.sample(n, psi, W.uniforms(200000, seed=2))
+    counts = np.bincount(shots.astype(np.int64), minlength=1 << n)
+    exp = p * len(shots)
+    keep = exp > 5
+    chi2 = np.sum((counts[keep] - exp[keep]) ** 2 / exp[keep])
+    assert chi2 < keep.sum() + 6 * np.sqrt(2 * keep.sum())
