@@ -22,7 +22,7 @@ HOST_SOURCES = ["gates.cpp", "fuse.cpp", "plan.cpp", "abi.cpp", "batch.cpp", "se
 DEVICE_SOURCES = ["kernels.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
-          f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
+          f"-I{os.path.join(ROOT, 'include')}"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
@@ -34,9 +34,11 @@ def _run(cmd):
     return out
 
 
-def build(verbose: bool = False, out: str | None = None, extra_flags=()) -> str:
-    """Compile and link; `out` and `extra_flags` (e.g. -DQSIM_LDS_SWIZZLE=0)
-    build a variant library elsewhere for comparisons."""
+def build(verbose: bool = False, out: str | None = None, extra_flags=(), csrc: str | None = None) -> str:
+    """Compile and link; `out`, `extra_flags` (e.g. -DQSIM_LDS_SWIZZLE=0) and
+    `csrc` (another source directory) build a variant library elsewhere for
+    comparisons."""
+    CSRC_ = csrc or CSRC
     lib_out = out or LIB
     build_dir = BUILD if out is None else out + ".build"
     os.makedirs(build_dir, exist_ok=True)
@@ -45,18 +47,18 @@ def build(verbose: bool = False, out: str | None = None, extra_flags=()) -> str:
     jobs = []
     objs = []
     for src in HOST_SOURCES:
-        path = os.path.join(CSRC, src)
+        path = os.path.join(CSRC_, src)
         if not os.path.exists(path):
             continue
         obj = os.path.join(build_dir, src + ".o")
         objs.append(obj)
-        jobs.append([clang, *COMMON, *extra_flags, "-D__HIP_PLATFORM_AMD__", f"-I{os.path.join(ROCM, 'include')}",
+        jobs.append([clang, *COMMON, f"-I{CSRC_}", *extra_flags, "-D__HIP_PLATFORM_AMD__", f"-I{os.path.join(ROCM, 'include')}",
                      "-pthread", "-c", path, "-o", obj])
     for src in DEVICE_SOURCES:
-        path = os.path.join(CSRC, src)
+        path = os.path.join(CSRC_, src)
         obj = os.path.join(build_dir, src + ".o")
         objs.append(obj)
-        jobs.append([hipcc, *HIP_FLAGS, *COMMON, *extra_flags, "-c", path, "-o", obj])
+        jobs.append([hipcc, *HIP_FLAGS, *COMMON, f"-I{CSRC_}", *extra_flags, "-c", path, "-o", obj])
     with cf.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
         for out in ex.map(_run, jobs):
             if verbose and out.strip():

@@ -51,7 +51,8 @@ void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc
     pc->tile_qubits = env_int("QSIM_TILE_QUBITS", dtype == QSIM_C64 ? 13 : 12);
     pc->low_qubits = env_int("QSIM_LOW_QUBITS", dtype == QSIM_C64 ? 4 : 3);
     pc->window = env_int("QSIM_PLAN_WINDOW", 1024);
-    pc->max_tile_k = dtype == QSIM_C64 ? 5 : 4;
+    pc->max_tile_k = 4;
+    pc->threads = env_int("QSIM_TILE_THREADS", 512) == 256 ? 256 : 512;
     if (opt) {
         if (opt->level >= 0 && opt->level <= 5) fc->level = opt->level;
         if (opt->max_width > 0) fc->max_width = opt->max_width;
@@ -72,13 +73,9 @@ void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc
     if (n <= resident_max(dtype)) pc->tile_qubits = n;
     if (pc->tile_qubits > n) pc->tile_qubits = n;
     pc->low_qubits = std::max(0, std::min(pc->low_qubits, pc->tile_qubits - 1));
-    // LDS behind the tile for the pass's records and coefficients: keep two
-    // workgroups per CU for tiles up to 64 KiB, else use what is left
-    const size_t tile_bytes = (size_t(1) << pc->tile_qubits) * elem_bytes(dtype);
-    const size_t lds = qk::max_lds_bytes() - 1024;
-    pc->meta_budget = tile_bytes <= 64 * 1024 ? std::min<size_t>(16 * 1024, lds - tile_bytes)
-                                              : lds - tile_bytes;
-    pc->meta_budget = std::min<size_t>(pc->meta_budget, size_t(env_int("QSIM_META_BUDGET", 1 << 30)));
+    // a pass's records and coefficients are read through the scalar cache:
+    // bound their bytes so that one pass's set stays resident there
+    pc->meta_budget = size_t(std::max(1024, env_int("QSIM_META_BUDGET", 16 * 1024)));
 }
 
 // Check, before anything is launched, that every device record stays inside
@@ -114,9 +111,7 @@ int validate_plan(int n, int dtype, const Compiled &c) {
         }
         if (p.pass_begin[i] > p.pass_begin[i + 1] || p.pass_begin[i + 1] > p.ops.size()) return QSIM_E_ARG;
         if (p.coef_begin[i] > p.coef_begin[i + 1] || p.coef_begin[i + 1] > p.coefs.size()) return QSIM_E_ARG;
-        if (!pi.strided &&
-            qk::tile_lds_bytes(elem_bytes(dtype), pi.ta.t, p.pass_begin[i + 1] - p.pass_begin[i],
-                               p.coef_begin[i + 1] - p.coef_begin[i]) > qk::max_lds_bytes() - 1024)
+        if (!pi.strided && qk::tile_lds_bytes(elem_bytes(dtype), pi.ta.t) > qk::max_lds_bytes())
             return QSIM_E_ARG;
         for (uint32_t j = p.pass_begin[i]; j < p.pass_begin[i + 1]; j++) {
             const DevOp &o = p.ops[j];
@@ -126,7 +121,7 @@ int validate_plan(int n, int dtype, const Compiled &c) {
                 continue;
             }
             if (o.k < 1 || o.k > kMaxK || o.k > width) return QSIM_E_ARG;
-            if (!pi.strided && dtype == QSIM_C128 && o.k > 4) return QSIM_E_ARG;
+            if (!pi.strided && o.k > 4) return QSIM_E_ARG;
             for (int a = 0; a < o.k; a++) {
                 if (o.pos[a] >= width) return QSIM_E_ARG;
                 if (a && o.pos[a] <= o.pos[a - 1]) return QSIM_E_ARG;
@@ -186,6 +181,7 @@ int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const doubl
         uint64_t all = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
         pi.ta.rest_mask = all & ~p.tile_mask;
         pi.ta.tile_mask = p.tile_mask;
+        pi.ta.threads = pc.threads;
         for (int h = 0; h < p.nhi; h++) pi.ta.hi[h] = uint8_t(p.hi[h]);
         out->passes.push_back(pi);
     }

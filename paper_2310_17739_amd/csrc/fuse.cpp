@@ -18,6 +18,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <new>
+#include <thread>
 
 #include "host.h"
 
@@ -334,11 +337,240 @@ void fuse_width(int n, Lowered *L, const FuseConfig &cfg) {
     L->op_epoch.swap(out_ep);
 }
 
+// Cost of an operator list under the level-5 model.
+double list_cost(const std::vector<Op> &ops, const FuseConfig &cfg) {
+    const double tol = 1e-14;
+    double c = 0;
+    for (const Op &o : ops) c += (cfg.sparse ? op_terms(o, tol) : (1 << o.k)) + cfg.lds_cost;
+    return c;
+}
+
+// An operator of at most kMaxK qubits in XOR-shift form,
+//   y[r] = sum over m in present of d[m][r] * x[r ^ m],
+// used to evaluate the products of many candidate runs cheaply: a gate with
+// few terms multiplies in (its terms x our terms x 2^k) MACs.  Only the rows
+// d[m] of present m are meaningful.
+struct XOp {
+    int k = 0;
+    int q[kMaxK] = {0, 0, 0, 0, 0};
+    uint32_t present = 0;
+    cd d[1 << kMaxK][1 << kMaxK];
+};
+
+inline int gather_bits(int r, const int *sel, int k) {
+    int out = 0;
+    for (int j = 0; j < k; j++) out |= ((r >> sel[j]) & 1) << j;
+    return out;
+}
+inline int scatter_bits(int m, const int *sel, int k) {
+    int out = 0;
+    for (int j = 0; j < k; j++) out |= ((m >> j) & 1) << sel[j];
+    return out;
+}
+
+// Bit m set when M[r][r ^ m] != 0 for some r (exact zeros only).
+uint32_t exact_present(const Op &o) {
+    const int D = o.dim();
+    uint32_t p = 0;
+    for (int m = 0; m < D; m++)
+        for (int r = 0; r < D; r++)
+            if (o.m[size_t(r) * D + (r ^ m)] != cd(0)) { p |= 1u << m; break; }
+    return p;
+}
+
+void xop_from(const Op &o, uint32_t present, XOp *x) {
+    x->k = o.k;
+    for (int j = 0; j < o.k; j++) x->q[j] = o.q[j];
+    x->present = present;
+    const int D = o.dim();
+    for (uint32_t pm = present; pm; pm &= pm - 1) {
+        const int m = __builtin_ctz(pm);
+        for (int r = 0; r < D; r++) x->d[m][r] = o.m[size_t(r) * D + (r ^ m)];
+    }
+}
+
+// `a` re-expressed on the ascending qubit list uq (a superset of its own).
+void xop_expand(const XOp &a, const int *uq, int uk, XOp *out) {
+    int sel[kMaxK];
+    for (int j = 0; j < a.k; j++)
+        for (int i = 0; i < uk; i++)
+            if (uq[i] == a.q[j]) sel[j] = i;
+    out->k = uk;
+    for (int i = 0; i < uk; i++) out->q[i] = uq[i];
+    out->present = 0;
+    const int D = 1 << uk;
+    int gi[1 << kMaxK];
+    for (int r = 0; r < D; r++) gi[r] = gather_bits(r, sel, a.k);
+    for (uint32_t pm = a.present; pm; pm &= pm - 1) {
+        const int m = __builtin_ctz(pm);
+        const int mm = scatter_bits(m, sel, a.k);
+        out->present |= 1u << mm;
+        for (int r = 0; r < D; r++) out->d[mm][r] = a.d[m][gi[r]];
+    }
+}
+
+// out := G * cur with G = gate o (present terms gp) on a subset of cur's
+// qubits:  (G M)[r][r^g^m] += G[r][r^g] M_m[r^g].
+void xop_left_mul(const Op &o, uint32_t gp, const XOp &cur, XOp *out) {
+    const int D = 1 << cur.k, Do = o.dim();
+    int sel[kMaxK];
+    for (int j = 0; j < o.k; j++)
+        for (int i = 0; i < cur.k; i++)
+            if (cur.q[i] == o.q[j]) sel[j] = i;
+    int gi[1 << kMaxK];
+    for (int r = 0; r < D; r++) gi[r] = gather_bits(r, sel, o.k);
+    out->k = cur.k;
+    std::copy(cur.q, cur.q + kMaxK, out->q);
+    out->present = 0;
+    for (uint32_t pg = gp; pg; pg &= pg - 1) {
+        const int gm = __builtin_ctz(pg);
+        const int gmm = scatter_bits(gm, sel, o.k);
+        cd gd[1 << kMaxK];
+        for (int r = 0; r < D; r++) gd[r] = o.m[size_t(gi[r]) * Do + (gi[r] ^ gm)];
+        for (uint32_t pm = cur.present; pm; pm &= pm - 1) {
+            const int m = __builtin_ctz(pm);
+            const int t = gmm ^ m;
+            if (!(out->present & (1u << t))) {
+                out->present |= 1u << t;
+                for (int r = 0; r < D; r++) out->d[t][r] = cd(0);
+            }
+            for (int r = 0; r < D; r++) {
+                const cd a = gd[r], b = cur.d[m][r ^ gmm];
+                out->d[t][r] += cd(a.real() * b.real() - a.imag() * b.imag(),
+                                   a.real() * b.imag() + a.imag() * b.real());
+            }
+        }
+    }
+}
+
+// Terms above rel_tol times the largest entry (as op_terms counts them).
+int xop_terms(const XOp &x, double rel_tol) {
+    const int D = 1 << x.k;
+    double rmax[1 << kMaxK];
+    double mx = 0;
+    int nt = 0;
+    for (uint32_t pm = x.present; pm; pm &= pm - 1) {
+        const cd *row = x.d[__builtin_ctz(pm)];
+        double v = 0;
+        for (int r = 0; r < D; r++) v = std::max(v, std::max(std::fabs(row[r].real()), std::fabs(row[r].imag())));
+        rmax[nt++] = v;
+        mx = std::max(mx, v);
+    }
+    const double tol = rel_tol * mx;
+    int n = 0;
+    for (int i = 0; i < nt; i++) n += rmax[i] > tol;
+    return n;
+}
+
+// Ascending union of two ascending qubit lists (stops past kMaxK).
+int union_lists(const int *a, int ka, const int *b, int kb, int *uq) {
+    int n = 0, i = 0, j = 0;
+    while (i < ka || j < kb) {
+        int x;
+        if (j >= kb || (i < ka && a[i] < b[j])) x = a[i++];
+        else if (i >= ka || b[j] < a[i]) x = b[j++];
+        else { x = a[i++]; j++; }
+        uq[n++] = x;
+        if (n > kMaxK) return n;
+    }
+    return n;
+}
+
+// Level 5, second candidate: the cheapest partition of the operator list into
+// runs of consecutive operators, each run merged into one operator of at most
+// max_width qubits (dynamic programming over run ends, same cost model).  A
+// run's partial products may be dense -- half of a CNOT ladder -- while the
+// whole run is sparse -- the Pauli-string exponential the ladder implements
+// -- which a merge judged one step at a time does not reach.
+void fuse_runs(Lowered *L, const FuseConfig &cfg) {
+    const double tol = 1e-14;
+    const size_t N = L->ops.size();
+    const int kMaxRun = 64;
+    std::vector<double> best(N + 1, 1e300);
+    std::vector<int> from(N + 1, -1);
+    best[0] = 0;
+    bool any_params = false;
+    for (const Op &o : L->ops) any_params = any_params || o.np > 0;
+    auto relax = [&](size_t s, size_t e, int terms, int k) {
+        const double c = best[s] + (cfg.sparse ? terms : (1 << k)) + cfg.lds_cost;
+        if (c < best[e]) {
+            best[e] = c;
+            from[e] = int(s);
+        }
+    };
+    if (!any_params) {
+        // products of runs in XOR-shift form (no angle slots to carry)
+        std::vector<uint32_t> gp(N);
+        for (size_t i = 0; i < N; i++) gp[i] = exact_present(L->ops[i]);
+        std::unique_ptr<XOp> buf0(new XOp), buf1(new XOp);
+        for (size_t s = 0; s < N; s++) {
+            if (best[s] >= 1e299) continue;
+            XOp *cur = buf0.get(), *nxt = buf1.get();
+            xop_from(L->ops[s], gp[s], cur);
+            relax(s, s + 1, xop_terms(*cur, tol), cur->k);
+            for (size_t e = s + 2; e <= N && int(e - s) <= kMaxRun; e++) {
+                const Op &o = L->ops[e - 1];
+                if (L->op_epoch[e - 1] != L->op_epoch[s]) break;
+                int uq[2 * kMaxK];
+                const int uk = union_lists(cur->q, cur->k, o.q, o.k, uq);
+                if (uk > cfg.max_width) break;
+                if (uk != cur->k) {
+                    xop_expand(*cur, uq, uk, nxt);
+                    std::swap(cur, nxt);
+                }
+                xop_left_mul(o, gp[e - 1], *cur, nxt);
+                std::swap(cur, nxt);
+                relax(s, e, xop_terms(*cur, tol), cur->k);
+            }
+        }
+    } else {
+        for (size_t s = 0; s < N; s++) {
+            if (best[s] >= 1e299) continue;
+            Op cur = L->ops[s];
+            for (size_t e = s + 1; e <= N && int(e - s) <= kMaxRun; e++) {
+                if (e > s + 1) {
+                    const Op &o = L->ops[e - 1];
+                    if (L->op_epoch[e - 1] != L->op_epoch[s]) break;
+                    if (cur.np + o.np > cfg.max_params) break;
+                    int uq[2 * kMaxK];
+                    const int uk = union_qubits(cur, o, uq);
+                    if (uk > cfg.max_width) break;
+                    cur = expand(cur, uq, uk);
+                    mul_small(&cur, o, true);
+                }
+                relax(s, e, cfg.sparse ? op_terms(cur, tol) : 0, cur.k);
+            }
+        }
+    }
+    // rebuild the chosen runs, last to first
+    std::vector<std::pair<int, int>> runs;
+    for (int e = int(N); e > 0; e = from[e]) runs.push_back({from[e], e});
+    std::reverse(runs.begin(), runs.end());
+    std::vector<Op> out;
+    std::vector<int> out_ep;
+    out.reserve(runs.size());
+    for (const auto &r : runs) {
+        Op cur = L->ops[size_t(r.first)];
+        for (int i = r.first + 1; i < r.second; i++) {
+            int uq[2 * kMaxK];
+            const int uk = union_qubits(cur, L->ops[size_t(i)], uq);
+            cur = expand(cur, uq, uk);
+            mul_small(&cur, L->ops[size_t(i)], true);
+        }
+        out_ep.push_back(L->op_epoch[size_t(r.first)]);
+        out.push_back(std::move(cur));
+    }
+    L->ops.swap(out);
+    L->op_epoch.swap(out_ep);
+}
+
 }  // namespace
 
 void fuse(int n, Lowered *L, const FuseConfig &cfg, int64_t counts[6]) {
     for (int l = 0; l < 6; l++) counts[l] = -1;
     counts[0] = int64_t(L->ops.size());
+    Lowered runs;
+    if (cfg.level >= 5) runs = *L;
     if (cfg.level >= 1) { fuse_f1(n, L, cfg); counts[1] = int64_t(L->ops.size()); }
     if (cfg.level >= 2) { fuse_f3(n, L, cfg); counts[2] = int64_t(L->ops.size()); }
     if (cfg.level == 3) {
@@ -356,7 +588,28 @@ void fuse(int n, Lowered *L, const FuseConfig &cfg, int64_t counts[6]) {
         compact(L);
         counts[3] = counts[4] = int64_t(L->ops.size());
     }
-    if (cfg.level >= 5) { fuse_width(n, L, cfg); counts[5] = int64_t(L->ops.size()); }
+    if (cfg.level >= 5) {
+        // two candidates, the cheaper under the cost model wins: the greedy
+        // merge of the F1-F4 operators (any that commute into place) and the
+        // best partition of the unfused gate list into runs of consecutive
+        // gates
+        // (independent: computed side by side)
+        bool runs_ok = true;
+        std::thread th([&runs, &cfg, &runs_ok] {
+            try {
+                fuse_runs(&runs, cfg);
+            } catch (const std::bad_alloc &) {
+                runs_ok = false;
+            }
+        });
+        fuse_width(n, L, cfg);
+        th.join();
+        if (runs_ok && list_cost(runs.ops, cfg) < list_cost(L->ops, cfg)) {
+            L->ops.swap(runs.ops);
+            L->op_epoch.swap(runs.op_epoch);
+        }
+        counts[5] = int64_t(L->ops.size());
+    }
 }
 
 }  // namespace qs

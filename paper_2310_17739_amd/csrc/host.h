@@ -107,7 +107,8 @@ struct PlanConfig {
     int low_qubits = 3;
     int window = 1024;            // lookahead when filling a pass
     int max_tile_k = 5;           // widest operator the tile kernel applies
-    size_t meta_budget = 16384;   // LDS bytes for a pass's operator records and coefficients
+    size_t meta_budget = 16384;   // bytes of a pass's operator records and coefficients
+    int threads = 512;            // tile kernel workgroup size (256 or 512)
     bool one_op_per_pass = false;
 };
 

@@ -46,24 +46,48 @@ __device__ __forceinline__ void cmac(Cx<T> &acc, const Cx<T> c, const Cx<T> x) {
     acc.im = fma(c.im, x.re, acc.im);
 }
 
+#ifndef APPLY_CHUNK_C128
+#define APPLY_CHUNK_C128 2
+#endif
+
+template <int V>
+struct IntC {
+    static constexpr int value = V;
+};
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(IntC<B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
 // y[r] = sum over present shifts m of d_m[r] * x[r ^ m]; cf holds the present
-// diagonals in ascending m, 2^K entries each.
-template <typename T, int K>
-__device__ __forceinline__ void apply_group(const Cx<T> (&x)[1 << K], Cx<T> (&y)[1 << K],
+// diagonals in ascending m, 2^K entries each.  Outputs R0 .. R0+RC-1 only, so
+// that a caller can store one chunk before computing the next and keep fewer
+// registers live; every output sums its terms in ascending m.
+template <typename T, int K, int R0, int RC>
+__device__ __forceinline__ void apply_chunk(const Cx<T> (&x)[1 << K], Cx<T> (&y)[RC],
                                             uint32_t present, const Cx<T> *__restrict__ cf) {
     constexpr int D = 1 << K;
 #pragma unroll
-    for (int r = 0; r < D; r++) y[r] = Cx<T>{T(0), T(0)};
+    for (int r = 0; r < RC; r++) y[r] = Cx<T>{T(0), T(0)};
     int ti = 0;
 #pragma unroll
     for (int m = 0; m < D; m++) {
         if (present & (1u << m)) {
-            const Cx<T> *c = cf + ti * D;
+            const Cx<T> *c = cf + ti * D + R0;
 #pragma unroll
-            for (int r = 0; r < D; r++) cmac(y[r], c[r], x[r ^ m]);
+            for (int r = 0; r < RC; r++) cmac(y[r], c[r], x[(R0 + r) ^ m]);
             ti++;
         }
     }
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void apply_group(const Cx<T> (&x)[1 << K], Cx<T> (&y)[1 << K],
+                                            uint32_t present, const Cx<T> *__restrict__ cf) {
+    apply_chunk<T, K, 0, (1 << K)>(x, y, present, cf);
 }
 
 // ------------------------------------------------------------ reductions
@@ -74,9 +98,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Sum of `v` over the workgroup, identical on every thread, fixed order.
-template <int NV>
+template <int NV, int NW = NWAVES>
 __device__ __forceinline__ void block_sum(double (&v)[NV]) {
-    __shared__ double red[NV][NWAVES];
+    __shared__ double red[NV][NW];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < NV; i++) {
@@ -88,7 +112,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
     for (int i = 0; i < NV; i++) {
         double s = 0;
 #pragma unroll
-        for (int j = 0; j < NWAVES; j++) s += red[i][j];
+        for (int j = 0; j < NW; j++) s += red[i][j];
         v[i] = s;
     }
     __syncthreads();
@@ -100,12 +124,13 @@ __device__ __forceinline__ double norm2(const Cx<T> a) {
     return re * re + im * im;
 }
 
-// LDS bank swizzle of tile element j: the low bits of j are XORed with a fold
-// of its higher bits, so that the power-of-two strides of a group's members
-// spread over the banks.  A bijection on [0, 2^t).  16-byte elements (complex
-// double) fold 3 bits, 8-byte elements fold 4.
+// Optional LDS bank swizzle of tile element j (build with
+// -DQSIM_LDS_SWIZZLE=1): the low bits of j are XORed with a fold of its
+// higher bits, so that the power-of-two strides of a group's members spread
+// over the banks.  A bijection on [0, 2^t).  Measured slower than the plain
+// layout on gfx950 for the benchmark circuits, so it is off by default.
 #ifndef QSIM_LDS_SWIZZLE
-#define QSIM_LDS_SWIZZLE 1
+#define QSIM_LDS_SWIZZLE 0
 #endif
 template <typename T>
 __device__ __forceinline__ int sw(int j) {
@@ -125,11 +150,14 @@ struct OpRec {
     int pos[5];
 };
 
-__device__ __forceinline__ OpRec decode_op(uint4 w) {
-    w.x = __builtin_amdgcn_readfirstlane(w.x);
-    w.y = __builtin_amdgcn_readfirstlane(w.y);
-    w.z = __builtin_amdgcn_readfirstlane(w.z);
-    w.w = __builtin_amdgcn_readfirstlane(w.w);
+// The record at a workgroup-uniform address: four words read as scalar loads
+// (readfirstlane tells the compiler they are uniform).
+__device__ __forceinline__ OpRec decode_op(const uint32_t *__restrict__ p) {
+    uint4 w;
+    w.x = __builtin_amdgcn_readfirstlane(p[0]);
+    w.y = __builtin_amdgcn_readfirstlane(p[1]);
+    w.z = __builtin_amdgcn_readfirstlane(p[2]);
+    w.w = __builtin_amdgcn_readfirstlane(p[3]);
     OpRec o;
     o.coef = w.x;
     o.present = w.y;
@@ -143,7 +171,7 @@ __device__ __forceinline__ OpRec decode_op(uint4 w) {
     return o;
 }
 
-template <typename T, int K>
+template <typename T, int K, int TNT>
 __device__ __forceinline__ void apply_lds(Cx<T> *__restrict__ s, int t, const OpRec &op,
                                           const Cx<T> *__restrict__ cf) {
     constexpr int D = 1 << K;
@@ -155,16 +183,23 @@ __device__ __forceinline__ void apply_lds(Cx<T> *__restrict__ s, int t, const Op
 #pragma unroll
     for (int r = 1; r < D; r++) off[r] = off[r & (r - 1)] + (1 << p[__builtin_ctz(r)]);
     const int ngroups = 1 << (t - K);
-    for (int g = threadIdx.x; g < ngroups; g += NT) {
+    for (int g = threadIdx.x; g < ngroups; g += TNT) {
         int base = g;
 #pragma unroll
         for (int j = 0; j < K; j++) base = ((base >> p[j]) << (p[j] + 1)) | (base & ((1 << p[j]) - 1));
-        Cx<T> x[D], y[D];
+        Cx<T> x[D];
 #pragma unroll
         for (int r = 0; r < D; r++) x[r] = s[sw<T>(base + off[r])];
-        apply_group<T, K>(x, y, op.present, cf);
+        // complex128 computes and stores the outputs in chunks of RC to keep
+        // its register count (and so its occupancy) close to complex64's
+        constexpr int RC = (sizeof(T) == 8 && D > APPLY_CHUNK_C128) ? APPLY_CHUNK_C128 : D;
+        static_for<0, D / RC>([&](auto ci) {
+            constexpr int R0 = decltype(ci)::value * RC;
+            Cx<T> y[RC];
+            apply_chunk<T, K, R0, RC>(x, y, op.present, cf);
 #pragma unroll
-        for (int r = 0; r < D; r++) s[sw<T>(base + off[r])] = y[r];
+            for (int r = 0; r < RC; r++) s[sw<T>(base + off[R0 + r])] = y[r];
+        });
     }
 }
 
@@ -188,21 +223,21 @@ __device__ __forceinline__ uint64_t deposit(uint64_t x, uint64_t m) {
 
 // Measurement, assertion and reset inside a resident program (t == n, so the
 // LDS index is the amplitude index).  Returns 0 or a negative status.
-template <typename T>
+template <typename T, int TNT>
 __device__ int lds_measure(Cx<T> *__restrict__ s, int t, const OpRec &op, const MeasArgs &ma,
                            uint32_t b) {
     const int q = op.pos[0];
     const int slot = int(op.coef);
     const int TN = 1 << t;
     double w[2] = {0.0, 0.0};
-    for (int j = threadIdx.x; j < TN; j += NT) w[(j >> q) & 1] += norm2(s[sw<T>(j)]);
-    block_sum<2>(w);
+    for (int j = threadIdx.x; j < TN; j += TNT) w[(j >> q) & 1] += norm2(s[sw<T>(j)]);
+    block_sum<2, TNT / 64>(w);
     const double P0 = w[0], P1 = w[1];
     if (op.kind == qs::DEVOP_RESET) {
         if (P1 == 0.0) return 0;
         if (P0 != 0.0) return QSIM_E_NOT_DEFINITE;
         const int half = TN >> 1;
-        for (int g = threadIdx.x; g < half; g += NT) {
+        for (int g = threadIdx.x; g < half; g += TNT) {
             const int lo = ((g >> q) << (q + 1)) | (g & ((1 << q) - 1));
             s[sw<T>(lo)] = s[sw<T>(lo | (1 << q))];
             s[sw<T>(lo | (1 << q))] = Cx<T>{T(0), T(0)};
@@ -227,7 +262,7 @@ __device__ int lds_measure(Cx<T> *__restrict__ s, int t, const OpRec &op, const 
         ma.outcomes[idx] = o;
         ma.probs[idx] = kept / (P0 + P1);
     }
-    for (int j = threadIdx.x; j < TN; j += NT) {
+    for (int j = threadIdx.x; j < TN; j += TNT) {
         Cx<T> a = s[sw<T>(j)];
         if (((j >> q) & 1) == o) { a.re *= scale; a.im *= scale; }
         else a = Cx<T>{T(0), T(0)};
@@ -236,17 +271,18 @@ __device__ int lds_measure(Cx<T> *__restrict__ s, int t, const OpRec &op, const 
     return 0;
 }
 
-// One tile of 2^t amplitudes per workgroup (blockIdx.x: tile, blockIdx.y:
-// state of a batch).  Element j of the tile (j = tid + i * NT, E = 2^LE
-// elements per thread) lives at amplitude  base | deposit(j, tile_mask),
+// One tile of 2^t amplitudes per workgroup of TNT threads (blockIdx.x:
+// tile, blockIdx.y: state of a batch).  Element j of the tile
+// (j = tid + i * TNT, E = 2^LE elements per thread) lives at amplitude
+// base | deposit(j, tile_mask),
 // where base deposits the tile index into the other qubits.
 //
-// The pass's operator records and coefficients ([ob, oe) and [cb, ce)) are
-// copied into LDS behind the tile, so that no operator waits on a global
-// load; their loads and the E tile loads per thread are all issued before
-// the first LDS write.
-template <typename T, int LE>
-__global__ void __launch_bounds__(NT) k_tile(Cx<T> *__restrict__ state, uint64_t sstride,
+// The pass's operator records [ob, oe) and its coefficients are read straight
+// from global memory at workgroup-uniform addresses, so that they arrive in
+// scalar registers through the scalar cache (every lane uses the same
+// coefficient at a time) and the LDS holds the tile alone.
+template <typename T, int LE, int TNT>
+__global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_t sstride,
                                              TileArgs ta, const uint4 *__restrict__ ops,
                                              uint32_t ob, uint32_t oe,
                                              const Cx<T> *__restrict__ coefs, uint32_t cb,
@@ -255,40 +291,32 @@ __global__ void __launch_bounds__(NT) k_tile(Cx<T> *__restrict__ state, uint64_t
     constexpr int E = 1 << LE;
     extern __shared__ __align__(16) unsigned char smem[];
     Cx<T> *s = reinterpret_cast<Cx<T> *>(smem);
-    const int TN = 1 << ta.t;
-    uint4 *lops = reinterpret_cast<uint4 *>(smem + size_t(TN) * sizeof(Cx<T>));
-    Cx<T> *lcf = reinterpret_cast<Cx<T> *>(lops + (oe - ob));
     const uint32_t b = blockIdx.y;
     Cx<T> *st = state + size_t(b) * sstride;
-    const Cx<T> *cfg = coefs + size_t(b) * cstride + cb;
+    const Cx<T> *cfs = coefs + size_t(b) * cstride;
     const int tid = threadIdx.x;
-    const bool active = (E > 1) || (tid < TN);
+    const bool active = (E > 1) || (tid < (1 << ta.t));
     if (ma.status && ma.status[b] != 0) return;   // an earlier step of this state failed
 
-    // operator records and coefficients of the pass: first into registers
-    constexpr int MR = 4;   // records / coefficients per thread held across the tile loads
-    const int nrec = int(oe - ob), ncf = int(ce - cb);
-    uint4 rr[MR];
-    Cx<T> cr[MR];
-#pragma unroll
-    for (int m = 0; m < MR; m++) {
-        const int x = tid + m * NT;
-        if (x < nrec) rr[m] = ops[ob + x];
-        if (x < ncf) cr[m] = cfg[x];
-    }
-
+    const int nrec = int(oe - ob);
     const uint64_t base = deposit(blockIdx.x, ta.rest_mask);
-    // thread part: the 8 low bits of j; iteration part: the bits above
+    // thread part: the low log2(TNT) bits of j; iteration part: the bits above
+    constexpr int LOGT = (TNT == 512) ? 9 : 8;
     uint64_t toff = 0;
 #pragma unroll
-    for (int bt = 0; bt < 8; bt++)
+    for (int bt = 0; bt < LOGT; bt++)
         if ((tid >> bt) & 1) toff |= nth_bit(ta.tile_mask, bt);
     uint64_t ibit[LE > 0 ? LE : 1];
 #pragma unroll
-    for (int bt = 0; bt < LE; bt++) ibit[bt] = nth_bit(ta.tile_mask, 8 + bt);
+    for (int bt = 0; bt < LE; bt++) ibit[bt] = nth_bit(ta.tile_mask, LOGT + bt);
 
-    Cx<T> v[E];
-    if (!(flags & TF_INIT_ZERO)) {
+    if (flags & TF_INIT_ZERO) {
+#pragma unroll
+        for (int i = 0; i < E; i++)
+            if (active) s[sw<T>(tid + i * TNT)] = Cx<T>{T((base == 0 && tid == 0 && i == 0) ? 1 : 0), T(0)};
+    } else {
+        // all E tile loads are in flight before the first LDS write
+        Cx<T> v[E];
 #pragma unroll
         for (int i = 0; i < E; i++) {
             uint64_t io = 0;
@@ -297,43 +325,31 @@ __global__ void __launch_bounds__(NT) k_tile(Cx<T> *__restrict__ state, uint64_t
                 if ((i >> bt) & 1) io |= ibit[bt];
             if (active) v[i] = st[base | toff | io];
         }
-    }
-#pragma unroll
-    for (int m = 0; m < MR; m++) {
-        const int x = tid + m * NT;
-        if (x < nrec) lops[x] = rr[m];
-        if (x < ncf) lcf[x] = cr[m];
-    }
-    for (int x = tid + MR * NT; x < nrec; x += NT) lops[x] = ops[ob + x];
-    for (int x = tid + MR * NT; x < ncf; x += NT) lcf[x] = cfg[x];
-    if (flags & TF_INIT_ZERO) {
 #pragma unroll
         for (int i = 0; i < E; i++)
-            if (active) s[sw<T>(tid + i * NT)] = Cx<T>{T((base == 0 && tid == 0 && i == 0) ? 1 : 0), T(0)};
-    } else {
-#pragma unroll
-        for (int i = 0; i < E; i++)
-            if (active) s[sw<T>(tid + i * NT)] = v[i];
+            if (active) s[sw<T>(tid + i * TNT)] = v[i];
     }
     __syncthreads();
 
     int status = 0;
     int i = 0;
     for (; i < nrec; i++) {
-        const OpRec op = decode_op(lops[i]);
+        const OpRec op = decode_op(reinterpret_cast<const uint32_t *>(ops + ob + i));
         if (op.kind == qs::DEVOP_MAT) {
-            const Cx<T> *cf = lcf + (op.coef - cb);
+            const Cx<T> *cf = cfs + op.coef;
+            // operators of up to 4 qubits (wider ones run as strided sweeps,
+            // which keeps the kernel's registers low enough for the occupancy
+            // the tile's LDS allows)
             switch (op.k) {
-            case 1: apply_lds<T, 1>(s, ta.t, op, cf); break;
-            case 2: apply_lds<T, 2>(s, ta.t, op, cf); break;
-            case 3: apply_lds<T, 3>(s, ta.t, op, cf); break;
-            case 4: apply_lds<T, 4>(s, ta.t, op, cf); break;
-            default:
-                if constexpr (sizeof(T) == 4) apply_lds<T, 5>(s, ta.t, op, cf);
-                break;
+            case 1: apply_lds<T, 1, TNT>(s, ta.t, op, cf); break;
+            case 2: apply_lds<T, 2, TNT>(s, ta.t, op, cf); break;
+            case 3: apply_lds<T, 3, TNT>(s, ta.t, op, cf); break;
+            default: apply_lds<T, 4, TNT>(s, ta.t, op, cf); break;
             }
         } else {
-            status = lds_measure<T>(s, ta.t, op, ma, b);
+            // the same on every lane: keeps the loop (and the record
+            // addresses) uniform
+            status = __builtin_amdgcn_readfirstlane(lds_measure<T, TNT>(s, ta.t, op, ma, b));
         }
         __syncthreads();
         if (status) break;
@@ -343,9 +359,10 @@ __global__ void __launch_bounds__(NT) k_tile(Cx<T> *__restrict__ state, uint64_t
         if (ma.fail_at) ma.fail_at[b] = int(ob) + i;
     }
     if (!(flags & TF_NO_STORE)) {
+        Cx<T> v[E];
 #pragma unroll
         for (int i2 = 0; i2 < E; i2++)
-            if (active) v[i2] = s[sw<T>(tid + i2 * NT)];
+            if (active) v[i2] = s[sw<T>(tid + i2 * TNT)];
 #pragma unroll
         for (int i2 = 0; i2 < E; i2++) {
             uint64_t io = 0;
@@ -647,9 +664,9 @@ uint32_t grid_for(uint64_t work) {
 
 size_t max_lds_bytes() { return 160 * 1024; }
 
-template <typename T, int LE>
+template <typename T, int LE, int TNT>
 static void lds_attr() {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<T, LE>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<T, LE, TNT>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(max_lds_bytes()));
     if (e != hipSuccess) note_hip(e, "hipFuncSetAttribute(k_tile)");
 }
@@ -660,33 +677,71 @@ int init_kernels() {
     // Allow the tile kernels the largest dynamic LDS they use (160 KiB).  The
     // attribute is advisory on this platform: a refusal is recorded, and a
     // launch that then asks for too much LDS reports its own error.
-    lds_attr<float, 0>();
-    lds_attr<float, 1>();
-    lds_attr<float, 2>();
-    lds_attr<float, 3>();
-    lds_attr<float, 4>();
-    lds_attr<float, 5>();
-    lds_attr<float, 6>();
-    lds_attr<double, 0>();
-    lds_attr<double, 1>();
-    lds_attr<double, 2>();
-    lds_attr<double, 3>();
-    lds_attr<double, 4>();
-    lds_attr<double, 5>();
+    lds_attr<float, 0, 256>();
+    lds_attr<float, 1, 256>();
+    lds_attr<float, 2, 256>();
+    lds_attr<float, 3, 256>();
+    lds_attr<float, 4, 256>();
+    lds_attr<float, 5, 256>();
+    lds_attr<float, 6, 256>();
+    lds_attr<float, 0, 512>();
+    lds_attr<float, 1, 512>();
+    lds_attr<float, 2, 512>();
+    lds_attr<float, 3, 512>();
+    lds_attr<float, 4, 512>();
+    lds_attr<float, 5, 512>();
+    lds_attr<float, 6, 512>();
+    lds_attr<double, 0, 256>();
+    lds_attr<double, 1, 256>();
+    lds_attr<double, 2, 256>();
+    lds_attr<double, 3, 256>();
+    lds_attr<double, 4, 256>();
+    lds_attr<double, 5, 256>();
+    lds_attr<double, 6, 256>();
+    lds_attr<double, 0, 512>();
+    lds_attr<double, 1, 512>();
+    lds_attr<double, 2, 512>();
+    lds_attr<double, 3, 512>();
+    lds_attr<double, 4, 512>();
+    lds_attr<double, 5, 512>();
+    lds_attr<double, 6, 512>();
     (void)hipGetLastError();
     done = 1;
     return QSIM_OK;
 }
 
-template <typename T, int LE>
+template <typename T, int LE, int TNT>
 static void tile_t(void *state, uint64_t sstride, uint32_t nstates, const TileArgs &ta,
                    const DevOp *ops, uint32_t ob, uint32_t oe, const void *coefs, uint32_t cb,
                    uint32_t ce, uint64_t cstride, const MeasArgs &m, uint32_t flags,
                    hipStream_t st) {
     const dim3 grid(uint32_t(uint64_t(1) << (ta.n - ta.t)), nstates);
-    const size_t lds = tile_lds_bytes(sizeof(Cx<T>), ta.t, oe - ob, ce - cb);
-    hipLaunchKernelGGL((k_tile<T, LE>), grid, dim3(NT), lds, st, (Cx<T> *)state, sstride, ta,
+    const size_t lds = tile_lds_bytes(sizeof(Cx<T>), ta.t);
+    hipLaunchKernelGGL((k_tile<T, LE, TNT>), grid, dim3(TNT), lds, st, (Cx<T> *)state, sstride, ta,
                        (const uint4 *)ops, ob, oe, (const Cx<T> *)coefs, cb, ce, cstride, m, flags);
+}
+
+template <typename T, int TNT>
+static int tile_dispatch_t(void *state, uint64_t sstride, uint32_t nstates, const TileArgs &ta,
+                           const DevOp *ops, uint32_t ob, uint32_t oe, const void *coefs,
+                           uint32_t cb, uint32_t ce, uint64_t cstride, const MeasArgs &m,
+                           uint32_t flags, hipStream_t st) {
+    constexpr int LOGT = (TNT == 512) ? 9 : 8;
+    const int le = ta.t > LOGT ? ta.t - LOGT : 0;
+#define QK_TILE_CASE(L)                                                                              \
+    case L: tile_t<T, L, TNT>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st); break;
+    switch (le) {
+        QK_TILE_CASE(0)
+        QK_TILE_CASE(1)
+        QK_TILE_CASE(2)
+        QK_TILE_CASE(3)
+        QK_TILE_CASE(4)
+        QK_TILE_CASE(5)
+        QK_TILE_CASE(6)
+    default: return QSIM_E_ARG;
+    }
+#undef QK_TILE_CASE
+    return QSIM_OK;
 }
 
 template <typename T>
@@ -694,23 +749,12 @@ static int tile_dispatch(void *state, uint64_t sstride, uint32_t nstates, const 
                          const DevOp *ops, uint32_t ob, uint32_t oe, const void *coefs,
                          uint32_t cb, uint32_t ce, uint64_t cstride, const MeasArgs &m,
                          uint32_t flags, hipStream_t st) {
-    const int le = ta.t > 8 ? ta.t - 8 : 0;
-    switch (le) {
-    case 0: tile_t<T, 0>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st); break;
-    case 1: tile_t<T, 1>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st); break;
-    case 2: tile_t<T, 2>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st); break;
-    case 3: tile_t<T, 3>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st); break;
-    case 4: tile_t<T, 4>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st); break;
-    case 5: tile_t<T, 5>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st); break;
-    case 6: tile_t<T, 6>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st); break;
-    default: return QSIM_E_ARG;
-    }
-    return QSIM_OK;
+    if (ta.threads == 512)
+        return tile_dispatch_t<T, 512>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st);
+    return tile_dispatch_t<T, 256>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st);
 }
 
-size_t tile_lds_bytes(size_t elem, int t, uint32_t nops, uint32_t ncoefs) {
-    return (size_t(1) << t) * elem + size_t(nops) * 16 + size_t(ncoefs) * elem;
-}
+size_t tile_lds_bytes(size_t elem, int t) { return (size_t(1) << t) * elem; }
 
 int launch_tile(int dtype, void *state, uint64_t sstride, uint32_t nstates, const TileArgs &ta,
                 const DevOp *ops, uint32_t ob, uint32_t oe, const void *coefs, uint32_t cb,
@@ -718,8 +762,9 @@ int launch_tile(int dtype, void *state, uint64_t sstride, uint32_t nstates, cons
                 hipStream_t st) {
     MeasArgs m{};
     if (ma) m = *ma;
-    if (ta.t < 1 || ta.t > 14 || ta.t > ta.n || ce < cb || oe < ob) return QSIM_E_ARG;
-    if (tile_lds_bytes(dtype == QSIM_C64 ? 8 : 16, ta.t, oe - ob, ce - cb) > max_lds_bytes())
+    if (ta.t < 1 || ta.t > 14 || ta.t > ta.n || ce < cb || oe < ob || (ta.threads != 256 && ta.threads != 512))
+        return QSIM_E_ARG;
+    if (tile_lds_bytes(dtype == QSIM_C64 ? 8 : 16, ta.t) > max_lds_bytes())
         return QSIM_E_CAPACITY;
     int rc = (dtype == QSIM_C64)
                  ? tile_dispatch<float>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st)

@@ -20,6 +20,8 @@ struct TileArgs {
     uint64_t rest_mask;   // qubits not in the tile
     uint64_t tile_mask;   // qubits in the tile (j bit b <-> b-th lowest of them)
     int32_t n, t, c, nhi;
+    int32_t threads;      // workgroup size of the tile kernel: 256 or 512
+    int32_t pad;
     uint8_t hi[48];
 };
 
@@ -41,9 +43,8 @@ enum : uint32_t { TF_INIT_ZERO = 1, TF_NO_STORE = 2 };
 int init_kernels();
 size_t max_lds_bytes();
 
-// LDS bytes of a tile pass: the tile, then the pass's operator records and
-// coefficients.
-size_t tile_lds_bytes(size_t elem, int t, uint32_t nops, uint32_t ncoefs);
+// LDS bytes of a tile pass (the tile alone).
+size_t tile_lds_bytes(size_t elem, int t);
 
 // One tiled pass (or a whole resident program when t == n) over `nstates`
 // states spaced `sstride` elements apart: operator records [ob, oe) whose

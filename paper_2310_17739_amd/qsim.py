@@ -27,8 +27,10 @@ F_ONE_OP_PER_PASS, F_NO_SPARSE = 1, 2
 class QsimError(RuntimeError):
     def __init__(self, code: int, what: str = ""):
         msg = _lib.qsim_strerror(code).decode() if _lib is not None else str(code)
-        if code == E_HIP and _lib is not None:
-            msg += " [" + _lib.qsim_last_error().decode() + "]"
+        if code in (E_HIP, E_NOMEM) and _lib is not None:
+            last = _lib.qsim_last_error().decode()
+            if last:
+                msg += " [" + last + "]"
         super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
         self.code = code
 
@@ -56,6 +58,13 @@ class qsim_apply_stats(C.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'`")
+    # torch ships its own HIP runtime under the soname libamdhip64.so.7 but
+    # asks for it as libamdhip64.so, so the loader cannot match the two:
+    # loading this library first would map ROCm's runtime as well, and the
+    # second runtime then finds no device.  Loading torch first makes this
+    # library bind to torch's runtime, which also lets torch streams and
+    # device pointers be passed straight through.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     P, I, SZ, D = C.c_void_p, C.c_int, C.c_size_t, C.c_double
     sig = {

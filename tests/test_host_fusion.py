@@ -5,12 +5,16 @@ oracle as dense matrix records; the result must equal the unfused circuit
 run by the oracle (fusion is exact matrix algebra, Section 3.2: the update
 need not be unitary, which is what makes fusion possible).
 """
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 import workloads as W
 from paper_2310_17739_amd import qsim
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def fused_as_records(ops):
@@ -163,3 +167,21 @@ def test_abi_exports_every_declared_symbol():
     lib = ctypes.CDLL(qsim.LIB_PATH)
     missing = [s for s in qsim.exported_symbols() if not hasattr(lib, s)]
     assert not missing, missing
+
+
+def test_one_hip_runtime_after_import():
+    """Importing the binding in a fresh process (before anything else loads
+    torch) maps a single HIP runtime: the library shares torch's."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2310_17739_amd import qsim\n"
+            "import torch\n"
+            "paths = set()\n"
+            "for line in open('/proc/self/maps'):\n"
+            "    p = line.split()[-1]\n"
+            "    if 'libamdhip64' in p: paths.add(p)\n"
+            "print(len(paths), sorted(paths))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.split()[0] == "1", out.stdout
