@@ -26,6 +26,26 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the tile kernel at 21 qubits, from two counter runs
+# of this benchmark (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE; KiB per
+# dispatch).  A plain 128 MiB device copy dispatch reads FETCH_SIZE = 65,543 KiB
+# and WRITE_SIZE = 131,072 KiB, so fetches scale by 2.0 and writes by 1.0.
+# The figures hold for the kernel source with the hash below; for any other
+# source the traffic is reported as null.
+MEASURED_TRAFFIC = {
+    "kernels_sha256_16": "c04b72001477edcd",
+    "complex128": (16573.7 * 2.0 + 32768.0) * 1024,
+    "complex64": (8328.5 * 2.0 + 16384.0) * 1024,
+}
+
+
+def measured_traffic(dtype):
+    import hashlib
+    src = os.path.join(ROOT, "paper_2310_17739_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()[:16]
+    return MEASURED_TRAFFIC.get(dtype) if h == MEASURED_TRAFFIC["kernels_sha256_16"] else None
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -215,7 +235,10 @@ def main():
     ap.add_argument("--n-exp", type=int, default=50_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the passes as a HIP graph")
-    ap.add_argument("--also", action="store_true", help="also measure the other dtype")
+    ap.add_argument("--only", action="store_true", help="skip the other dtype")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 256 MiB device copy five times (a known byte count for "
+                         "scaling memory counters)")
     ap.add_argument("--forms", default="", help="comma list of extra forms to run: "
                     "trajectories,batched,served,wide (or 'all')")
     args = ap.parse_args()
@@ -229,6 +252,15 @@ def main():
 
     import workloads as W
     from paper_2310_17739_amd import qsim
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")   # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 5 x 256 MiB read + 256 MiB written")
+        del src, dst
 
     n = args.qubits
     log(f"[bench] generating circuit: {n} qubits, {args.n_exp} exponentials")
@@ -250,35 +282,52 @@ def main():
             sv.qsim_expval(H)
         log(f"[bench] {dtype}: warmup done; timing {args.steps} steps")
         torch.cuda.synchronize()
-        kern_ms = []
+        # events on the stream the passes run on (the state's stream is
+        # torch's current stream), around each step's program
+        stream = sv.stream
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
         t0 = time.perf_counter()
         energy = None
         for i in range(args.steps):
             sv.qsim_init_zero()
-            if args.graph:
-                prog.qsim_run(sv)
-            else:
-                prog.qsim_run_timed(sv)
+            ev[i][0].record(stream)
+            prog.qsim_run(sv)
+            ev[i][1].record(stream)
             energy = sv.qsim_expval(H)      # synchronises the stream
-            if not args.graph:
-                ms, launches = prog.qsim_program_kernel_ms()
-                kern_ms.append(ms)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        prog_ms = [a.elapsed_time(b) for a, b in ev]
         ms_step = 1e3 * dt / args.steps
         elem = 16 if dtype == "complex128" else 8
         pass_bytes = 2 * elem * (1 << n)
         res = {"dtype": dtype, "ms_per_step": ms_step, "gates_per_s": st["input_gates"] / (dt / args.steps),
                "compile_s": compile_s, "stats": st, "energy": energy, "norm": sv.qsim_norm()}
-        if kern_ms:
-            avg_ms = float(np.mean(kern_ms)) / st["passes"]
+        if not args.graph:
+            # average launch duration over the timed region: the program's
+            # span divided by its launches (inter-launch gaps included)
+            launches = st["passes"]
+            avg_ms = float(np.mean(prog_ms)) / launches
             achieved = pass_bytes / (avg_ms * 1e-3) / 1e9
-            res["kernel_ms_per_step"] = float(np.mean(kern_ms))
-            res["avg_pass_us"] = avg_ms * 1e3
+            res["program_ms_per_step"] = float(np.mean(prog_ms))
+            res["avg_launch_us"] = avg_ms * 1e3
             res["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                               "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                               "kernel": f"k_tile<{'double' if elem == 16 else 'float'}>",
-                               "bytes_per_launch": pass_bytes}
+                               "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dtype),
+                               "kernel": f"k_tile<{'double' if elem == 16 else 'float'}, LE, 512>",
+                               "bytes_per_launch": pass_bytes, "launches_per_step": launches}
+            # one more step with an event pair around every pass: pure kernel
+            # time per launch (what a kernel trace reports)
+            sv.qsim_init_zero()
+            prog.qsim_run_timed(sv)
+            kms, kl = prog.qsim_program_kernel_ms()
+            res["per_pass_kernel_us"] = 1e3 * kms / kl
+            # arithmetic of the same launches: 8 flops per complex MAC, one
+            # MAC per amplitude per XOR-shift term
+            flops = 8.0 * st["terms"] * (1 << n)
+            res["alu"] = {"flops_per_step": flops,
+                          "achieved_TFLOPs": flops / (float(np.mean(prog_ms)) * 1e-3) / 1e12,
+                          "peak_TFLOPs": 78.6,
+                          "frac": flops / (float(np.mean(prog_ms)) * 1e-3) / 1e12 / 78.6}
         prog.close()
         sv.close()
         return res
@@ -295,7 +344,7 @@ def main():
             forms[name] = fn(qsim, W)
             log(f"[bench] {name}: {json.dumps(forms[name])}")
     other = None
-    if args.also:
+    if not args.only:
         other = measure("complex64" if args.dtype == "complex128" else "complex128")
     cpu = None
     if not args.no_cpu_baseline:
@@ -327,16 +376,16 @@ def main():
         "energy": main_res["energy"],
         "norm": main_res["norm"],
     }
-    if "kernel_ms_per_step" in main_res:
-        out["kernel_ms_per_step"] = main_res["kernel_ms_per_step"]
-        out["avg_pass_us"] = main_res["avg_pass_us"]
+    for k in ("program_ms_per_step", "avg_launch_us", "per_pass_kernel_us", "alu"):
+        if k in main_res:
+            out[k] = main_res[k]
     if forms:
         out["forms"] = forms
     if other is not None:
         out["other_dtype"] = {k: other[k] for k in ("dtype", "ms_per_step", "gates_per_s", "energy")}
-        if "roofline" in other:
-            out["other_dtype"]["roofline"] = other["roofline"]
-            out["other_dtype"]["avg_pass_us"] = other["avg_pass_us"]
+        for k in ("roofline", "avg_launch_us", "per_pass_kernel_us", "alu"):
+            if k in other:
+                out["other_dtype"][k] = other[k]
     print(json.dumps(out), flush=True)
 
 
