@@ -13,6 +13,7 @@
 #include "host.h"
 #include "launch.h"
 #include "runtime.h"
+#include "swizzle.h"
 
 using namespace qs;
 
@@ -52,7 +53,9 @@ void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc
     pc->low_qubits = env_int("QSIM_LOW_QUBITS", dtype == QSIM_C64 ? 4 : 3);
     pc->window = env_int("QSIM_PLAN_WINDOW", 1024);
     pc->max_tile_k = 4;
-    pc->threads = env_int("QSIM_TILE_THREADS", 512) == 256 ? 256 : 512;
+    // complex64 tiles use 512 threads; complex128 tiles 256, whose groups of
+    // 16 outputs then fit the registers without chunking
+    pc->threads = env_int("QSIM_TILE_THREADS", dtype == QSIM_C64 ? 512 : 256) == 256 ? 256 : 512;
     if (opt) {
         if (opt->level >= 0 && opt->level <= 5) fc->level = opt->level;
         if (opt->max_width > 0) fc->max_width = opt->max_width;
@@ -107,6 +110,12 @@ int validate_plan(int n, int dtype, const Compiled &c) {
                 m |= uint64_t(1) << ta.hi[h];
             }
             if ((m & ta.rest_mask) || ((m | ta.rest_mask) != all) || m != ta.tile_mask) return QSIM_E_ARG;
+            uint64_t mq = 0;
+            for (int j = 0; j < ta.t; j++) {
+                if (j && ta.tq[j] <= ta.tq[j - 1]) return QSIM_E_ARG;
+                mq |= uint64_t(1) << ta.tq[j];
+            }
+            if (mq != ta.tile_mask) return QSIM_E_ARG;
             width = ta.t;
         }
         if (p.pass_begin[i] > p.pass_begin[i + 1] || p.pass_begin[i + 1] > p.ops.size()) return QSIM_E_ARG;
@@ -125,6 +134,7 @@ int validate_plan(int n, int dtype, const Compiled &c) {
             for (int a = 0; a < o.k; a++) {
                 if (o.pos[a] >= width) return QSIM_E_ARG;
                 if (a && o.pos[a] <= o.pos[a - 1]) return QSIM_E_ARG;
+                if (!pi.strided && o.slot[a] != lds_slot(int(elem_bytes(dtype)), 1 << o.pos[a])) return QSIM_E_ARG;
             }
             const uint32_t d = 1u << o.k;
             const uint32_t mask = (d >= 32) ? 0xffffffffu : ((1u << d) - 1);
@@ -167,6 +177,15 @@ int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const doubl
     std::vector<Pass> passes;
     plan_passes(n, L, meta, pc, &passes);
     pack_plan(L.ops, present, passes, &out->plan);
+    // LDS slot offsets of the tile positions (the tile kernel's layout)
+    for (size_t i = 0; i < passes.size(); i++) {
+        if (passes[i].strided || passes[i].kind != Pass::TILE) continue;
+        for (uint32_t j = out->plan.pass_begin[i]; j < out->plan.pass_begin[i + 1]; j++) {
+            DevOp &o = out->plan.ops[j];
+            if (o.kind != DEVOP_MAT) continue;
+            for (int a = 0; a < o.k; a++) o.slot[a] = uint16_t(lds_slot(int(elem_bytes(dtype)), 1 << o.pos[a]));
+        }
+    }
     out->passes.clear();
     out->passes.reserve(passes.size());
     for (const Pass &p : passes) {
@@ -183,6 +202,11 @@ int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const doubl
         pi.ta.tile_mask = p.tile_mask;
         pi.ta.threads = pc.threads;
         for (int h = 0; h < p.nhi; h++) pi.ta.hi[h] = uint8_t(p.hi[h]);
+        {
+            int j = 0;
+            for (int q = 0; q < 64 && j < 16; q++)
+                if ((p.tile_mask >> q) & 1) pi.ta.tq[j++] = uint8_t(q);
+        }
         out->passes.push_back(pi);
     }
     qsim_apply_stats &s = out->stats;

@@ -120,7 +120,7 @@ void plan_passes(int n, const Lowered &L, const std::vector<uint32_t> &meta_byte
                  const PlanConfig &cfg, std::vector<Pass> *passes);
 
 // ---- packing into device tables (plan.cpp)
-// Device operator record (16 bytes): see kernels.hip.
+// Device operator record (32 bytes, read as eight scalar words): see kernels.hip.
 struct DevOp {
     uint32_t coef;     // offset of the first term's coefficients (complex elements)
     uint32_t present;  // bit m set: the XOR-shift-m diagonal is nonzero
@@ -128,8 +128,10 @@ struct DevOp {
     uint8_t pos[5];    // qubit positions (tile-local for tiled passes, global for strided)
     uint8_t kind;      // DEVOP_*
     uint8_t pad;
+    uint16_t slot[5];  // tiled passes: LDS slot offset of position j's bit, lds_slot(1 << pos[j])
+    uint16_t pad2[3];
 };
-static_assert(sizeof(DevOp) == 16, "DevOp layout");
+static_assert(sizeof(DevOp) == 32, "DevOp layout");
 
 enum { DEVOP_MAT = 0, DEVOP_MEASURE = 1, DEVOP_ASSERT0 = 2, DEVOP_RESET = 3 };
 

@@ -25,6 +25,7 @@
 #include <cstdint>
 
 #include "launch.h"
+#include "swizzle.h"
 
 namespace qk {
 
@@ -97,25 +98,31 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Sum of `v` over the workgroup, identical on every thread, fixed order.
-template <int NV, int NW = NWAVES>
-__device__ __forceinline__ void block_sum(double (&v)[NV]) {
-    __shared__ double red[NV][NW];
+// Sum of `v` over the workgroup, identical on every thread, fixed order;
+// `red` holds NV * NW doubles of LDS.
+template <int NV, int NW, typename P>
+__device__ __forceinline__ void block_sum_in(double (&v)[NV], P red) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < NV; i++) {
         double s = wave_sum(v[i]);
-        if (lane == 0) red[i][w] = s;
+        if (lane == 0) red[i * NW + w] = s;
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NV; i++) {
         double s = 0;
 #pragma unroll
-        for (int j = 0; j < NW; j++) s += red[i][j];
+        for (int j = 0; j < NW; j++) s += red[i * NW + j];
         v[i] = s;
     }
     __syncthreads();
+}
+
+template <int NV, int NW = NWAVES>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+    __shared__ double red[NV * NW];
+    block_sum_in<NV, NW>(v, &red[0]);
 }
 
 template <typename T>
@@ -124,89 +131,110 @@ __device__ __forceinline__ double norm2(const Cx<T> a) {
     return re * re + im * im;
 }
 
-// Optional LDS bank swizzle of tile element j (build with
-// -DQSIM_LDS_SWIZZLE=1): the low bits of j are XORed with a fold of its
-// higher bits, so that the power-of-two strides of a group's members spread
-// over the banks.  A bijection on [0, 2^t).  Measured slower than the plain
-// layout on gfx950 for the benchmark circuits, so it is off by default.
-#ifndef QSIM_LDS_SWIZZLE
-#define QSIM_LDS_SWIZZLE 0
-#endif
+// LDS slot of tile element j (the fold defined with the pass packer).
 template <typename T>
 __device__ __forceinline__ int sw(int j) {
-#if QSIM_LDS_SWIZZLE
-    if constexpr (sizeof(T) == 8) return j ^ (((j >> 3) ^ (j >> 6) ^ (j >> 9) ^ (j >> 12)) & 7);
-    else return j ^ (((j >> 4) ^ (j >> 8) ^ (j >> 12)) & 15);
-#else
-    return j;
-#endif
+    return qs::lds_slot(int(sizeof(Cx<T>)), j);
 }
 
+// The tile of k_tile sits at LDS byte 0 of its workgroup (the kernel has no
+// static LDS, which init_kernels checks), slot i at byte i * sizeof(Cx<T>),
+// and is addressed by byte offsets, so that an access costs one XOR; the FP64
+// reduction scratch of in-tile measurements follows the tile.
+template <typename T>
+struct LdsTile {
+    static constexpr int LOGE = sizeof(Cx<T>) == 8 ? 3 : 4;
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    static __device__ __forceinline__ Cx<T> ld(uint32_t byte) {
+        const V2 v = *reinterpret_cast<const __attribute__((address_space(3))) V2 *>(uintptr_t(byte));
+        return Cx<T>{v.x, v.y};
+    }
+    static __device__ __forceinline__ void st(uint32_t byte, Cx<T> c) {
+        V2 v;
+        v.x = c.re;
+        v.y = c.im;
+        *reinterpret_cast<__attribute__((address_space(3))) V2 *>(uintptr_t(byte)) = v;
+    }
+    static __device__ __forceinline__ Cx<T> at(int j) { return ld(uint32_t(sw<T>(j)) << LOGE); }
+    static __device__ __forceinline__ void set(int j, Cx<T> v) { st(uint32_t(sw<T>(j)) << LOGE, v); }
+    static __device__ __forceinline__ __attribute__((address_space(3))) double *red(int t) {
+        return reinterpret_cast<__attribute__((address_space(3))) double *>(uintptr_t(uint32_t(sizeof(Cx<T>)) << t));
+    }
+};
+
 // ------------------------------------------------------------ tile kernel
-// Operator record fields, read as one scalar dword quad (see qs::DevOp).
+// Operator record fields, read as eight scalar words (see qs::DevOp).
 struct OpRec {
     uint32_t coef, present;
     int k, kind;
     int pos[5];
+    int slot[5];
 };
 
-// The record at a workgroup-uniform address: four words read as scalar loads
-// (readfirstlane tells the compiler they are uniform).
+// The record at a workgroup-uniform address: eight words read as scalar
+// loads (readfirstlane tells the compiler they are uniform).
 __device__ __forceinline__ OpRec decode_op(const uint32_t *__restrict__ p) {
-    uint4 w;
-    w.x = __builtin_amdgcn_readfirstlane(p[0]);
-    w.y = __builtin_amdgcn_readfirstlane(p[1]);
-    w.z = __builtin_amdgcn_readfirstlane(p[2]);
-    w.w = __builtin_amdgcn_readfirstlane(p[3]);
+    uint32_t w[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) w[i] = __builtin_amdgcn_readfirstlane(p[i]);
     OpRec o;
-    o.coef = w.x;
-    o.present = w.y;
-    o.k = int(w.z & 0xff);
-    o.pos[0] = int((w.z >> 8) & 0xff);
-    o.pos[1] = int((w.z >> 16) & 0xff);
-    o.pos[2] = int(w.z >> 24);
-    o.pos[3] = int(w.w & 0xff);
-    o.pos[4] = int((w.w >> 8) & 0xff);
-    o.kind = int((w.w >> 16) & 0xff);
+    o.coef = w[0];
+    o.present = w[1];
+    o.k = int(w[2] & 0xff);
+    o.pos[0] = int((w[2] >> 8) & 0xff);
+    o.pos[1] = int((w[2] >> 16) & 0xff);
+    o.pos[2] = int(w[2] >> 24);
+    o.pos[3] = int(w[3] & 0xff);
+    o.pos[4] = int((w[3] >> 8) & 0xff);
+    o.kind = int((w[3] >> 16) & 0xff);
+    o.slot[0] = int(w[4] & 0xffff);
+    o.slot[1] = int(w[4] >> 16);
+    o.slot[2] = int(w[5] & 0xffff);
+    o.slot[3] = int(w[5] >> 16);
+    o.slot[4] = int(w[6] & 0xffff);
     return o;
 }
 
 template <typename T, int K, int TNT>
-__device__ __forceinline__ void apply_lds(Cx<T> *__restrict__ s, int t, const OpRec &op,
-                                          const Cx<T> *__restrict__ cf) {
+__device__ __forceinline__ void apply_lds(int t, const OpRec &op, const Cx<T> *__restrict__ cf) {
+    using L = LdsTile<T>;
     constexpr int D = 1 << K;
     int p[K];
 #pragma unroll
     for (int j = 0; j < K; j++) p[j] = op.pos[j];
-    int off[D];
+    // byte offsets of the group members' LDS slots from the first member's
+    // (the fold is linear: slot(base | off) = slot(base) ^ slot(off))
+    uint32_t off[D];
     off[0] = 0;
 #pragma unroll
-    for (int r = 1; r < D; r++) off[r] = off[r & (r - 1)] + (1 << p[__builtin_ctz(r)]);
+    for (int r = 1; r < D; r++) off[r] = off[r & (r - 1)] ^ (uint32_t(op.slot[__builtin_ctz(r)]) << L::LOGE);
     const int ngroups = 1 << (t - K);
     for (int g = threadIdx.x; g < ngroups; g += TNT) {
         int base = g;
 #pragma unroll
         for (int j = 0; j < K; j++) base = ((base >> p[j]) << (p[j] + 1)) | (base & ((1 << p[j]) - 1));
+        const uint32_t b0 = uint32_t(sw<T>(base)) << L::LOGE;
+        uint32_t addr[D];
         Cx<T> x[D];
 #pragma unroll
-        for (int r = 0; r < D; r++) x[r] = s[sw<T>(base + off[r])];
-        // complex128 computes and stores the outputs in chunks of RC to keep
-        // its register count (and so its occupancy) close to complex64's
-        constexpr int RC = (sizeof(T) == 8 && D > APPLY_CHUNK_C128) ? APPLY_CHUNK_C128 : D;
+        for (int r = 0; r < D; r++) {
+            addr[r] = b0 ^ off[r];
+            // keep the address in a register for the write-back (rather than
+            // recomputing it from the scalar offsets, which then stay live)
+            asm volatile("" : "+v"(addr[r]));
+            x[r] = L::ld(addr[r]);
+        }
+        // complex128 computes and stores the outputs in chunks of RC when
+        // 512 threads share the CU, to keep 4 waves per SIMD
+        constexpr int RC = (sizeof(T) == 8 && TNT == 512 && D > APPLY_CHUNK_C128) ? APPLY_CHUNK_C128 : D;
         static_for<0, D / RC>([&](auto ci) {
             constexpr int R0 = decltype(ci)::value * RC;
             Cx<T> y[RC];
             apply_chunk<T, K, R0, RC>(x, y, op.present, cf);
 #pragma unroll
-            for (int r = 0; r < RC; r++) s[sw<T>(base + off[R0 + r])] = y[r];
+            for (int r = 0; r < RC; r++) L::st(addr[R0 + r], y[r]);
         });
     }
-}
-
-// The b-th lowest set bit of m, as a one-bit mask (0 if m has fewer bits).
-__device__ __forceinline__ uint64_t nth_bit(uint64_t m, int b) {
-    for (int i = 0; i < b && m; i++) m &= m - 1;
-    return m & (~m + 1);
 }
 
 // Scatter the low bits of x into the set bits of m, in ascending order.
@@ -224,14 +252,14 @@ __device__ __forceinline__ uint64_t deposit(uint64_t x, uint64_t m) {
 // Measurement, assertion and reset inside a resident program (t == n, so the
 // LDS index is the amplitude index).  Returns 0 or a negative status.
 template <typename T, int TNT>
-__device__ int lds_measure(Cx<T> *__restrict__ s, int t, const OpRec &op, const MeasArgs &ma,
-                           uint32_t b) {
+__device__ int lds_measure(int t, const OpRec &op, const MeasArgs &ma, uint32_t b) {
+    using L = LdsTile<T>;
     const int q = op.pos[0];
     const int slot = int(op.coef);
     const int TN = 1 << t;
     double w[2] = {0.0, 0.0};
-    for (int j = threadIdx.x; j < TN; j += TNT) w[(j >> q) & 1] += norm2(s[sw<T>(j)]);
-    block_sum<2, TNT / 64>(w);
+    for (int j = threadIdx.x; j < TN; j += TNT) w[(j >> q) & 1] += norm2(L::at(j));
+    block_sum_in<2, TNT / 64>(w, L::red(t));
     const double P0 = w[0], P1 = w[1];
     if (op.kind == qs::DEVOP_RESET) {
         if (P1 == 0.0) return 0;
@@ -239,8 +267,8 @@ __device__ int lds_measure(Cx<T> *__restrict__ s, int t, const OpRec &op, const 
         const int half = TN >> 1;
         for (int g = threadIdx.x; g < half; g += TNT) {
             const int lo = ((g >> q) << (q + 1)) | (g & ((1 << q) - 1));
-            s[sw<T>(lo)] = s[sw<T>(lo | (1 << q))];
-            s[sw<T>(lo | (1 << q))] = Cx<T>{T(0), T(0)};
+            L::set(lo, L::at(lo | (1 << q)));
+            L::set(lo | (1 << q), Cx<T>{T(0), T(0)});
         }
         return 0;
     }
@@ -263,12 +291,30 @@ __device__ int lds_measure(Cx<T> *__restrict__ s, int t, const OpRec &op, const 
         ma.probs[idx] = kept / (P0 + P1);
     }
     for (int j = threadIdx.x; j < TN; j += TNT) {
-        Cx<T> a = s[sw<T>(j)];
+        Cx<T> a = L::at(j);
         if (((j >> q) & 1) == o) { a.re *= scale; a.im *= scale; }
         else a = Cx<T>{T(0), T(0)};
-        s[sw<T>(j)] = a;
+        L::set(j, a);
     }
     return 0;
+}
+
+// Tile loads and stores of the state stream past the caches (non-temporal):
+// each pass touches every amplitude once, and the operator records and
+// coefficients read through the scalar cache then stay resident in L2.
+template <typename T>
+__device__ __forceinline__ Cx<T> ld_stream(const Cx<T> *p) {
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    const V2 v = __builtin_nontemporal_load(reinterpret_cast<const V2 *>(p));
+    return Cx<T>{v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(Cx<T> *p, Cx<T> c) {
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    V2 v;
+    v.x = c.re;
+    v.y = c.im;
+    __builtin_nontemporal_store(v, reinterpret_cast<V2 *>(p));
 }
 
 // One tile of 2^t amplitudes per workgroup of TNT threads (blockIdx.x:
@@ -283,14 +329,13 @@ __device__ int lds_measure(Cx<T> *__restrict__ s, int t, const OpRec &op, const 
 // coefficient at a time) and the LDS holds the tile alone.
 template <typename T, int LE, int TNT>
 __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_t sstride,
-                                             TileArgs ta, const uint4 *__restrict__ ops,
+                                             TileArgs ta, const DevOp *__restrict__ ops,
                                              uint32_t ob, uint32_t oe,
                                              const Cx<T> *__restrict__ coefs, uint32_t cb,
                                              uint32_t ce, uint64_t cstride, MeasArgs ma,
                                              uint32_t flags) {
+    using L = LdsTile<T>;
     constexpr int E = 1 << LE;
-    extern __shared__ __align__(16) unsigned char smem[];
-    Cx<T> *s = reinterpret_cast<Cx<T> *>(smem);
     const uint32_t b = blockIdx.y;
     Cx<T> *st = state + size_t(b) * sstride;
     const Cx<T> *cfs = coefs + size_t(b) * cstride;
@@ -301,19 +346,24 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
     const int nrec = int(oe - ob);
     const uint64_t base = deposit(blockIdx.x, ta.rest_mask);
     // thread part: the low log2(TNT) bits of j; iteration part: the bits above
+    // (tile position j is qubit ta.tq[j])
     constexpr int LOGT = (TNT == 512) ? 9 : 8;
     uint64_t toff = 0;
 #pragma unroll
     for (int bt = 0; bt < LOGT; bt++)
-        if ((tid >> bt) & 1) toff |= nth_bit(ta.tile_mask, bt);
+        if (bt < ta.t && ((tid >> bt) & 1)) toff |= uint64_t(1) << ta.tq[bt];
     uint64_t ibit[LE > 0 ? LE : 1];
 #pragma unroll
-    for (int bt = 0; bt < LE; bt++) ibit[bt] = nth_bit(ta.tile_mask, LOGT + bt);
+    for (int bt = 0; bt < LE; bt++) ibit[bt] = uint64_t(1) << ta.tq[LOGT + bt];
 
+    // element tid + i * TNT sits at slot sw(tid) ^ sw(i * TNT)
+    const uint32_t stid = uint32_t(sw<T>(tid)) << L::LOGE;
     if (flags & TF_INIT_ZERO) {
 #pragma unroll
         for (int i = 0; i < E; i++)
-            if (active) s[sw<T>(tid + i * TNT)] = Cx<T>{T((base == 0 && tid == 0 && i == 0) ? 1 : 0), T(0)};
+            if (active)
+                L::st(stid ^ (uint32_t(sw<T>(i * TNT)) << L::LOGE),
+                      Cx<T>{T((base == 0 && tid == 0 && i == 0) ? 1 : 0), T(0)});
     } else {
         // all E tile loads are in flight before the first LDS write
         Cx<T> v[E];
@@ -323,33 +373,33 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
 #pragma unroll
             for (int bt = 0; bt < LE; bt++)
                 if ((i >> bt) & 1) io |= ibit[bt];
-            if (active) v[i] = st[base | toff | io];
+            if (active) v[i] = ld_stream(st + (base | toff | io));
         }
 #pragma unroll
         for (int i = 0; i < E; i++)
-            if (active) s[sw<T>(tid + i * TNT)] = v[i];
+            if (active) L::st(stid ^ (uint32_t(sw<T>(i * TNT)) << L::LOGE), v[i]);
     }
     __syncthreads();
 
     int status = 0;
     int i = 0;
     for (; i < nrec; i++) {
-        const OpRec op = decode_op(reinterpret_cast<const uint32_t *>(ops + ob + i));
+        const OpRec op = decode_op(reinterpret_cast<const uint32_t *>(ops) + size_t(ob + i) * (sizeof(DevOp) / 4));
         if (op.kind == qs::DEVOP_MAT) {
             const Cx<T> *cf = cfs + op.coef;
             // operators of up to 4 qubits (wider ones run as strided sweeps,
             // which keeps the kernel's registers low enough for the occupancy
             // the tile's LDS allows)
             switch (op.k) {
-            case 1: apply_lds<T, 1, TNT>(s, ta.t, op, cf); break;
-            case 2: apply_lds<T, 2, TNT>(s, ta.t, op, cf); break;
-            case 3: apply_lds<T, 3, TNT>(s, ta.t, op, cf); break;
-            default: apply_lds<T, 4, TNT>(s, ta.t, op, cf); break;
+            case 1: apply_lds<T, 1, TNT>(ta.t, op, cf); break;
+            case 2: apply_lds<T, 2, TNT>(ta.t, op, cf); break;
+            case 3: apply_lds<T, 3, TNT>(ta.t, op, cf); break;
+            default: apply_lds<T, 4, TNT>(ta.t, op, cf); break;
             }
         } else {
             // the same on every lane: keeps the loop (and the record
             // addresses) uniform
-            status = __builtin_amdgcn_readfirstlane(lds_measure<T, TNT>(s, ta.t, op, ma, b));
+            status = __builtin_amdgcn_readfirstlane(lds_measure<T, TNT>(ta.t, op, ma, b));
         }
         __syncthreads();
         if (status) break;
@@ -362,14 +412,14 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
         Cx<T> v[E];
 #pragma unroll
         for (int i2 = 0; i2 < E; i2++)
-            if (active) v[i2] = s[sw<T>(tid + i2 * TNT)];
+            if (active) v[i2] = L::ld(stid ^ (uint32_t(sw<T>(i2 * TNT)) << L::LOGE));
 #pragma unroll
         for (int i2 = 0; i2 < E; i2++) {
             uint64_t io = 0;
 #pragma unroll
             for (int bt = 0; bt < LE; bt++)
                 if ((i2 >> bt) & 1) io |= ibit[bt];
-            if (active) st[base | toff | io] = v[i2];
+            if (active) st_stream(st + (base | toff | io), v[i2]);
         }
     }
 }
@@ -664,11 +714,16 @@ uint32_t grid_for(uint64_t work) {
 
 size_t max_lds_bytes() { return 160 * 1024; }
 
+// The tile kernel addresses its LDS from byte 0: it must have no static LDS.
+static int tile_static_lds = 0;
+
 template <typename T, int LE, int TNT>
 static void lds_attr() {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<T, LE, TNT>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(max_lds_bytes()));
+    const void *f = reinterpret_cast<const void *>(&k_tile<T, LE, TNT>);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(max_lds_bytes()));
     if (e != hipSuccess) note_hip(e, "hipFuncSetAttribute(k_tile)");
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, f) == hipSuccess && fa.sharedSizeBytes != 0) tile_static_lds = 1;
 }
 
 int init_kernels() {
@@ -706,6 +761,10 @@ int init_kernels() {
     lds_attr<double, 5, 512>();
     lds_attr<double, 6, 512>();
     (void)hipGetLastError();
+    if (tile_static_lds) {
+        note_hip(hipErrorInvalidKernelFile, "k_tile declares static LDS (its tile must start at LDS byte 0)");
+        return QSIM_E_UNSUPPORTED;
+    }
     done = 1;
     return QSIM_OK;
 }
@@ -718,7 +777,7 @@ static void tile_t(void *state, uint64_t sstride, uint32_t nstates, const TileAr
     const dim3 grid(uint32_t(uint64_t(1) << (ta.n - ta.t)), nstates);
     const size_t lds = tile_lds_bytes(sizeof(Cx<T>), ta.t);
     hipLaunchKernelGGL((k_tile<T, LE, TNT>), grid, dim3(TNT), lds, st, (Cx<T> *)state, sstride, ta,
-                       (const uint4 *)ops, ob, oe, (const Cx<T> *)coefs, cb, ce, cstride, m, flags);
+                       ops, ob, oe, (const Cx<T> *)coefs, cb, ce, cstride, m, flags);
 }
 
 template <typename T, int TNT>
@@ -754,7 +813,7 @@ static int tile_dispatch(void *state, uint64_t sstride, uint32_t nstates, const 
     return tile_dispatch_t<T, 256>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st);
 }
 
-size_t tile_lds_bytes(size_t elem, int t) { return (size_t(1) << t) * elem; }
+size_t tile_lds_bytes(size_t elem, int t) { return (size_t(1) << t) * elem + kTileRedBytes; }
 
 int launch_tile(int dtype, void *state, uint64_t sstride, uint32_t nstates, const TileArgs &ta,
                 const DevOp *ops, uint32_t ob, uint32_t oe, const void *coefs, uint32_t cb,

@@ -22,6 +22,7 @@ struct TileArgs {
     int32_t n, t, c, nhi;
     int32_t threads;      // workgroup size of the tile kernel: 256 or 512
     int32_t pad;
+    uint8_t tq[16];       // qubit of tile position j (the tile qubits, ascending)
     uint8_t hi[48];
 };
 
@@ -43,7 +44,9 @@ enum : uint32_t { TF_INIT_ZERO = 1, TF_NO_STORE = 2 };
 int init_kernels();
 size_t max_lds_bytes();
 
-// LDS bytes of a tile pass (the tile alone).
+// LDS bytes of a tile pass: the tile, then the workgroup-reduction scratch
+// of in-tile measurements (2 values x up to 8 waves, FP64).
+constexpr size_t kTileRedBytes = 2 * 8 * sizeof(double);
 size_t tile_lds_bytes(size_t elem, int t);
 
 // One tiled pass (or a whole resident program when t == n) over `nstates`
