@@ -49,7 +49,7 @@ void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc
     fc->sparse = true;
     fc->max_params = 0;
     pc->one_op_per_pass = false;
-    pc->tile_qubits = env_int("QSIM_TILE_QUBITS", dtype == QSIM_C64 ? 13 : 12);
+    pc->tile_qubits = env_int("QSIM_TILE_QUBITS", 12);
     pc->low_qubits = env_int("QSIM_LOW_QUBITS", dtype == QSIM_C64 ? 4 : 3);
     pc->window = env_int("QSIM_PLAN_WINDOW", 1024);
     pc->max_tile_k = 4;
@@ -76,9 +76,11 @@ void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc
     if (n <= resident_max(dtype)) pc->tile_qubits = n;
     if (pc->tile_qubits > n) pc->tile_qubits = n;
     pc->low_qubits = std::max(0, std::min(pc->low_qubits, pc->tile_qubits - 1));
-    // a pass's records and coefficients are read through the scalar cache:
-    // bound their bytes so that one pass's set stays resident there
-    pc->meta_budget = size_t(std::max(1024, env_int("QSIM_META_BUDGET", 16 * 1024)));
+    // LDS behind the tile (and its reduction scratch) for a pass's records and
+    // coefficients: at most 16 KiB, and what the tile leaves
+    const size_t tile_bytes = (size_t(1) << pc->tile_qubits) * elem_bytes(dtype) + qk::kTileRedBytes;
+    const size_t room = qk::max_lds_bytes() > tile_bytes ? qk::max_lds_bytes() - tile_bytes : 0;
+    pc->meta_budget = std::min(room, size_t(std::max(1024, env_int("QSIM_META_BUDGET", 16 * 1024))));
 }
 
 // Check, before anything is launched, that every device record stays inside
@@ -120,7 +122,9 @@ int validate_plan(int n, int dtype, const Compiled &c) {
         }
         if (p.pass_begin[i] > p.pass_begin[i + 1] || p.pass_begin[i + 1] > p.ops.size()) return QSIM_E_ARG;
         if (p.coef_begin[i] > p.coef_begin[i + 1] || p.coef_begin[i + 1] > p.coefs.size()) return QSIM_E_ARG;
-        if (!pi.strided && qk::tile_lds_bytes(elem_bytes(dtype), pi.ta.t) > qk::max_lds_bytes())
+        if (!pi.strided &&
+            qk::tile_lds_bytes(elem_bytes(dtype), pi.ta.t, p.pass_begin[i + 1] - p.pass_begin[i],
+                               p.coef_begin[i + 1] - p.coef_begin[i]) > qk::max_lds_bytes())
             return QSIM_E_ARG;
         for (uint32_t j = p.pass_begin[i]; j < p.pass_begin[i + 1]; j++) {
             const DevOp &o = p.ops[j];
@@ -804,7 +808,7 @@ int qsim_autotune(qsim_h h, const qsim_gate *g, size_t ng, const double *mats, c
     // the prefix ends at a whole number of records; barriers are kept
     const size_t np = std::min(ng, prefix_gates);
     std::vector<qsim_fuse_opts> cands;
-    const int tdef = h->dtype == QSIM_C64 ? 13 : 12;
+    const int tdef = 12;
     const int ldef = h->dtype == QSIM_C64 ? 4 : 3;
     const int wmax = h->dtype == QSIM_C64 ? 5 : 4;
     for (int t : {tdef - 1, tdef, tdef + 1}) {

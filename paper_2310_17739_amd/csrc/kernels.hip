@@ -47,6 +47,15 @@ __device__ __forceinline__ void cmac(Cx<T> &acc, const Cx<T> c, const Cx<T> x) {
     acc.im = fma(c.im, x.re, acc.im);
 }
 
+// c * x, rounded exactly as cmac into a zero accumulator
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(const Cx<T> c, const Cx<T> x) {
+    Cx<T> r;
+    r.re = fma(-c.im, x.im, c.re * x.re);
+    r.im = fma(c.im, x.re, c.re * x.im);
+    return r;
+}
+
 #ifndef APPLY_CHUNK_C128
 #define APPLY_CHUNK_C128 2
 #endif
@@ -84,6 +93,12 @@ __device__ __forceinline__ void apply_chunk(const Cx<T> (&x)[1 << K], Cx<T> (&y)
         }
     }
 }
+
+// The same with the coefficients in LDS at byte address cfb (every lane
+// reads the same words: broadcast reads, completed in order).
+template <typename T, int K, int R0, int RC>
+__device__ __forceinline__ void apply_chunk_lds(const Cx<T> (&x)[1 << K], Cx<T> (&y)[RC],
+                                                uint32_t present, uint32_t cfb);
 
 template <typename T, int K>
 __device__ __forceinline__ void apply_group(const Cx<T> (&x)[1 << K], Cx<T> (&y)[1 << K],
@@ -171,12 +186,15 @@ struct OpRec {
     int slot[5];
 };
 
-// The record at a workgroup-uniform address: eight words read as scalar
-// loads (readfirstlane tells the compiler they are uniform).
-__device__ __forceinline__ OpRec decode_op(const uint32_t *__restrict__ p) {
-    uint32_t w[8];
+// The record at LDS byte address `at` (the same for every lane): eight words,
+// moved to scalar registers.
+__device__ __forceinline__ OpRec decode_op(uint32_t at) {
+    typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+    const U4 a = *reinterpret_cast<const __attribute__((address_space(3))) U4 *>(uintptr_t(at));
+    const U4 bq = *reinterpret_cast<const __attribute__((address_space(3))) U4 *>(uintptr_t(at + 16));
+    uint32_t w[8] = {a.x, a.y, a.z, a.w, bq.x, bq.y, bq.z, bq.w};
 #pragma unroll
-    for (int i = 0; i < 8; i++) w[i] = __builtin_amdgcn_readfirstlane(p[i]);
+    for (int i = 0; i < 8; i++) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
     OpRec o;
     o.coef = w[0];
     o.present = w[1];
@@ -195,8 +213,33 @@ __device__ __forceinline__ OpRec decode_op(const uint32_t *__restrict__ p) {
     return o;
 }
 
+template <typename T, int K, int R0, int RC>
+__device__ __forceinline__ void apply_chunk_lds(const Cx<T> (&x)[1 << K], Cx<T> (&y)[RC],
+                                                uint32_t present, uint32_t cfb) {
+    using L = LdsTile<T>;
+    constexpr int D = 1 << K;
+    uint32_t c = cfb + (uint32_t(R0) << L::LOGE);
+    // the main diagonal (present in most operators) starts the sums
+    if (present & 1u) {
+#pragma unroll
+        for (int r = 0; r < RC; r++) y[r] = cmul(L::ld(c + (uint32_t(r) << L::LOGE)), x[R0 + r]);
+        c += uint32_t(D) << L::LOGE;
+    } else {
+#pragma unroll
+        for (int r = 0; r < RC; r++) y[r] = Cx<T>{T(0), T(0)};
+    }
+#pragma unroll
+    for (int m = 1; m < D; m++) {
+        if (present & (1u << m)) {
+#pragma unroll
+            for (int r = 0; r < RC; r++) cmac(y[r], L::ld(c + (uint32_t(r) << L::LOGE)), x[(R0 + r) ^ m]);
+            c += uint32_t(D) << L::LOGE;
+        }
+    }
+}
+
 template <typename T, int K, int TNT>
-__device__ __forceinline__ void apply_lds(int t, const OpRec &op, const Cx<T> *__restrict__ cf) {
+__device__ __forceinline__ void apply_lds(int t, const OpRec &op, uint32_t cfb) {
     using L = LdsTile<T>;
     constexpr int D = 1 << K;
     int p[K];
@@ -230,7 +273,7 @@ __device__ __forceinline__ void apply_lds(int t, const OpRec &op, const Cx<T> *_
         static_for<0, D / RC>([&](auto ci) {
             constexpr int R0 = decltype(ci)::value * RC;
             Cx<T> y[RC];
-            apply_chunk<T, K, R0, RC>(x, y, op.present, cf);
+            apply_chunk_lds<T, K, R0, RC>(x, y, op.present, cfb);
 #pragma unroll
             for (int r = 0; r < RC; r++) L::st(addr[R0 + r], y[r]);
         });
@@ -323,10 +366,11 @@ __device__ __forceinline__ void st_stream(Cx<T> *p, Cx<T> c) {
 // base | deposit(j, tile_mask),
 // where base deposits the tile index into the other qubits.
 //
-// The pass's operator records [ob, oe) and its coefficients are read straight
-// from global memory at workgroup-uniform addresses, so that they arrive in
-// scalar registers through the scalar cache (every lane uses the same
-// coefficient at a time) and the LDS holds the tile alone.
+// The pass's operator records [ob, oe) and coefficients [cb, ce) are copied
+// into LDS behind the tile while the tile loads are in flight; an operator
+// then reads its record and coefficients as LDS broadcasts, which complete in
+// order and let its first multiply-adds start as soon as their own
+// coefficients arrive.
 template <typename T, int LE, int TNT>
 __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_t sstride,
                                              TileArgs ta, const DevOp *__restrict__ ops,
@@ -343,7 +387,10 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
     const bool active = (E > 1) || (tid < (1 << ta.t));
     if (ma.status && ma.status[b] != 0) return;   // an earlier step of this state failed
 
-    const int nrec = int(oe - ob);
+    const int nrec = int(oe - ob), ncf = int(ce - cb);
+    // LDS: the tile, the reduction scratch, the pass's records, its coefficients
+    const uint32_t rec_at = (uint32_t(sizeof(Cx<T>)) << ta.t) + uint32_t(kTileRedBytes);
+    const uint32_t cf_at = rec_at + uint32_t(nrec) * uint32_t(sizeof(DevOp));
     const uint64_t base = deposit(blockIdx.x, ta.rest_mask);
     // thread part: the low log2(TNT) bits of j; iteration part: the bits above
     // (tile position j is qubit ta.tq[j])
@@ -358,12 +405,18 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
 
     // element tid + i * TNT sits at slot sw(tid) ^ sw(i * TNT)
     const uint32_t stid = uint32_t(sw<T>(tid)) << L::LOGE;
+    typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+    const U4 *gops = reinterpret_cast<const U4 *>(ops + ob);
+    const Cx<T> *gcf = cfs + cb;
     if (flags & TF_INIT_ZERO) {
 #pragma unroll
         for (int i = 0; i < E; i++)
             if (active)
                 L::st(stid ^ (uint32_t(sw<T>(i * TNT)) << L::LOGE),
                       Cx<T>{T((base == 0 && tid == 0 && i == 0) ? 1 : 0), T(0)});
+        for (int x = tid; x < 2 * nrec; x += TNT)
+            *reinterpret_cast<__attribute__((address_space(3))) U4 *>(uintptr_t(rec_at + 16u * x)) = gops[x];
+        for (int x = tid; x < ncf; x += TNT) L::st(cf_at + (uint32_t(x) << L::LOGE), gcf[x]);
     } else {
         // all E tile loads are in flight before the first LDS write
         Cx<T> v[E];
@@ -375,6 +428,10 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
                 if ((i >> bt) & 1) io |= ibit[bt];
             if (active) v[i] = ld_stream(st + (base | toff | io));
         }
+        // the pass's records and coefficients follow while the tile loads fly
+        for (int x = tid; x < 2 * nrec; x += TNT)
+            *reinterpret_cast<__attribute__((address_space(3))) U4 *>(uintptr_t(rec_at + 16u * x)) = gops[x];
+        for (int x = tid; x < ncf; x += TNT) L::st(cf_at + (uint32_t(x) << L::LOGE), gcf[x]);
 #pragma unroll
         for (int i = 0; i < E; i++)
             if (active) L::st(stid ^ (uint32_t(sw<T>(i * TNT)) << L::LOGE), v[i]);
@@ -384,9 +441,9 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
     int status = 0;
     int i = 0;
     for (; i < nrec; i++) {
-        const OpRec op = decode_op(reinterpret_cast<const uint32_t *>(ops) + size_t(ob + i) * (sizeof(DevOp) / 4));
+        const OpRec op = decode_op(rec_at + uint32_t(i) * uint32_t(sizeof(DevOp)));
         if (op.kind == qs::DEVOP_MAT) {
-            const Cx<T> *cf = cfs + op.coef;
+            const uint32_t cf = cf_at + ((op.coef - cb) << L::LOGE);
             // operators of up to 4 qubits (wider ones run as strided sweeps,
             // which keeps the kernel's registers low enough for the occupancy
             // the tile's LDS allows)
@@ -775,7 +832,7 @@ static void tile_t(void *state, uint64_t sstride, uint32_t nstates, const TileAr
                    uint32_t ce, uint64_t cstride, const MeasArgs &m, uint32_t flags,
                    hipStream_t st) {
     const dim3 grid(uint32_t(uint64_t(1) << (ta.n - ta.t)), nstates);
-    const size_t lds = tile_lds_bytes(sizeof(Cx<T>), ta.t);
+    const size_t lds = tile_lds_bytes(sizeof(Cx<T>), ta.t, oe - ob, ce - cb);
     hipLaunchKernelGGL((k_tile<T, LE, TNT>), grid, dim3(TNT), lds, st, (Cx<T> *)state, sstride, ta,
                        ops, ob, oe, (const Cx<T> *)coefs, cb, ce, cstride, m, flags);
 }
@@ -813,7 +870,9 @@ static int tile_dispatch(void *state, uint64_t sstride, uint32_t nstates, const 
     return tile_dispatch_t<T, 256>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st);
 }
 
-size_t tile_lds_bytes(size_t elem, int t) { return (size_t(1) << t) * elem + kTileRedBytes; }
+size_t tile_lds_bytes(size_t elem, int t, uint32_t nrec, uint32_t ncoef) {
+    return (size_t(1) << t) * elem + kTileRedBytes + size_t(nrec) * sizeof(DevOp) + size_t(ncoef) * elem;
+}
 
 int launch_tile(int dtype, void *state, uint64_t sstride, uint32_t nstates, const TileArgs &ta,
                 const DevOp *ops, uint32_t ob, uint32_t oe, const void *coefs, uint32_t cb,
@@ -823,7 +882,7 @@ int launch_tile(int dtype, void *state, uint64_t sstride, uint32_t nstates, cons
     if (ma) m = *ma;
     if (ta.t < 1 || ta.t > 14 || ta.t > ta.n || ce < cb || oe < ob || (ta.threads != 256 && ta.threads != 512))
         return QSIM_E_ARG;
-    if (tile_lds_bytes(dtype == QSIM_C64 ? 8 : 16, ta.t) > max_lds_bytes())
+    if (tile_lds_bytes(dtype == QSIM_C64 ? 8 : 16, ta.t, oe - ob, ce - cb) > max_lds_bytes())
         return QSIM_E_CAPACITY;
     int rc = (dtype == QSIM_C64)
                  ? tile_dispatch<float>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st)

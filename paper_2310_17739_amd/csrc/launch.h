@@ -44,10 +44,11 @@ enum : uint32_t { TF_INIT_ZERO = 1, TF_NO_STORE = 2 };
 int init_kernels();
 size_t max_lds_bytes();
 
-// LDS bytes of a tile pass: the tile, then the workgroup-reduction scratch
-// of in-tile measurements (2 values x up to 8 waves, FP64).
+// LDS bytes of a tile pass: the tile, the workgroup-reduction scratch of
+// in-tile measurements (2 values x up to 8 waves, FP64), the pass's operator
+// records and its coefficients.
 constexpr size_t kTileRedBytes = 2 * 8 * sizeof(double);
-size_t tile_lds_bytes(size_t elem, int t);
+size_t tile_lds_bytes(size_t elem, int t, uint32_t nrec, uint32_t ncoef);
 
 // One tiled pass (or a whole resident program when t == n) over `nstates`
 // states spaced `sstride` elements apart: operator records [ob, oe) whose

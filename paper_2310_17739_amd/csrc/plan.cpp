@@ -29,7 +29,7 @@ void plan_passes(int n, const Lowered &L, const std::vector<uint32_t> &meta_byte
     const int c = std::min(cfg.low_qubits, t);
     const uint64_t all = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
     const uint64_t low = (uint64_t(1) << c) - 1;
-    constexpr uint32_t kMeasBytes = 16;
+    constexpr uint32_t kMeasBytes = sizeof(DevOp);   // a measurement record, no coefficients
 
     // operators of epoch e: [ep_begin[e], ep_begin[e + 1])
     std::vector<int> ep_begin(L.n_epochs + 1, N);
