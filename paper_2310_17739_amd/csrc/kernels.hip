@@ -238,35 +238,42 @@ __device__ __forceinline__ void apply_chunk_lds(const Cx<T> (&x)[1 << K], Cx<T> 
     }
 }
 
-template <typename T, int K, int TNT>
-__device__ __forceinline__ void apply_lds(int t, const OpRec &op, uint32_t cfb) {
+// Byte addresses of the members of a thread's first group (g = threadIdx.x)
+// for an operator of at most 4 qubits: they depend on its record only, so they
+// are computed before the barrier that ends the previous operator.  Entries
+// beyond 2^k are unused.
+template <typename T>
+__device__ __forceinline__ void prep_addr(const OpRec &op, uint32_t (&addr)[16]) {
     using L = LdsTile<T>;
-    constexpr int D = 1 << K;
-    int p[K];
+    int base = threadIdx.x;
 #pragma unroll
-    for (int j = 0; j < K; j++) p[j] = op.pos[j];
-    // byte offsets of the group members' LDS slots from the first member's
-    // (the fold is linear: slot(base | off) = slot(base) ^ slot(off))
-    uint32_t off[D];
+    for (int j = 0; j < 4; j++)
+        if (j < op.k) base = ((base >> op.pos[j]) << (op.pos[j] + 1)) | (base & ((1 << op.pos[j]) - 1));
+    const uint32_t b0 = uint32_t(sw<T>(base)) << L::LOGE;
+    // (the fold is linear: slot(base | off) = slot(base) ^ slot(off); slots
+    // beyond the operator's k are zero in the record)
+    uint32_t off[16];
     off[0] = 0;
 #pragma unroll
-    for (int r = 1; r < D; r++) off[r] = off[r & (r - 1)] ^ (uint32_t(op.slot[__builtin_ctz(r)]) << L::LOGE);
-    const int ngroups = 1 << (t - K);
-    for (int g = threadIdx.x; g < ngroups; g += TNT) {
-        int base = g;
+    for (int r = 1; r < 16; r++) off[r] = off[r & (r - 1)] ^ (uint32_t(op.slot[__builtin_ctz(r)]) << L::LOGE);
 #pragma unroll
-        for (int j = 0; j < K; j++) base = ((base >> p[j]) << (p[j] + 1)) | (base & ((1 << p[j]) - 1));
-        const uint32_t b0 = uint32_t(sw<T>(base)) << L::LOGE;
-        uint32_t addr[D];
+    for (int r = 0; r < 16; r++) {
+        addr[r] = b0 ^ off[r];
+        // keep the addresses in registers across the barrier and for the
+        // write-back
+        asm volatile("" : "+v"(addr[r]));
+    }
+}
+
+template <typename T, int K, int TNT>
+__device__ __forceinline__ void apply_lds(int t, const OpRec &op, uint32_t cfb, const uint32_t (&addr0)[16]) {
+    using L = LdsTile<T>;
+    constexpr int D = 1 << K;
+    const int ngroups = 1 << (t - K);
+    auto group = [&](const uint32_t (&addr)[D]) {
         Cx<T> x[D];
 #pragma unroll
-        for (int r = 0; r < D; r++) {
-            addr[r] = b0 ^ off[r];
-            // keep the address in a register for the write-back (rather than
-            // recomputing it from the scalar offsets, which then stay live)
-            asm volatile("" : "+v"(addr[r]));
-            x[r] = L::ld(addr[r]);
-        }
+        for (int r = 0; r < D; r++) x[r] = L::ld(addr[r]);
         // complex128 computes and stores the outputs in chunks of RC when
         // 512 threads share the CU, to keep 4 waves per SIMD
         constexpr int RC = (sizeof(T) == 8 && TNT == 512 && D > APPLY_CHUNK_C128) ? APPLY_CHUNK_C128 : D;
@@ -277,6 +284,34 @@ __device__ __forceinline__ void apply_lds(int t, const OpRec &op, uint32_t cfb) 
 #pragma unroll
             for (int r = 0; r < RC; r++) L::st(addr[R0 + r], y[r]);
         });
+    };
+    if (int(threadIdx.x) < ngroups) {
+        uint32_t addr[D];
+#pragma unroll
+        for (int r = 0; r < D; r++) addr[r] = addr0[r];
+        group(addr);
+    }
+    if (ngroups <= TNT) return;
+    // further groups of this thread (operators on fewer qubits)
+    int p[K];
+#pragma unroll
+    for (int j = 0; j < K; j++) p[j] = op.pos[j];
+    uint32_t off[D];
+    off[0] = 0;
+#pragma unroll
+    for (int r = 1; r < D; r++) off[r] = off[r & (r - 1)] ^ (uint32_t(op.slot[__builtin_ctz(r)]) << L::LOGE);
+    for (int g = threadIdx.x + TNT; g < ngroups; g += TNT) {
+        int base = g;
+#pragma unroll
+        for (int j = 0; j < K; j++) base = ((base >> p[j]) << (p[j] + 1)) | (base & ((1 << p[j]) - 1));
+        const uint32_t b0 = uint32_t(sw<T>(base)) << L::LOGE;
+        uint32_t addr[D];
+#pragma unroll
+        for (int r = 0; r < D; r++) {
+            addr[r] = b0 ^ off[r];
+            asm volatile("" : "+v"(addr[r]));
+        }
+        group(addr);
     }
 }
 
@@ -440,23 +475,34 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
 
     int status = 0;
     int i = 0;
+    // the next operator's record and addresses are prepared before the
+    // barrier that ends the current one
+    OpRec op{};
+    uint32_t addr[16];
+    if (nrec > 0) {
+        op = decode_op(rec_at);
+        if (op.kind == qs::DEVOP_MAT) prep_addr<T>(op, addr);
+    }
     for (; i < nrec; i++) {
-        const OpRec op = decode_op(rec_at + uint32_t(i) * uint32_t(sizeof(DevOp)));
         if (op.kind == qs::DEVOP_MAT) {
             const uint32_t cf = cf_at + ((op.coef - cb) << L::LOGE);
             // operators of up to 4 qubits (wider ones run as strided sweeps,
             // which keeps the kernel's registers low enough for the occupancy
             // the tile's LDS allows)
             switch (op.k) {
-            case 1: apply_lds<T, 1, TNT>(ta.t, op, cf); break;
-            case 2: apply_lds<T, 2, TNT>(ta.t, op, cf); break;
-            case 3: apply_lds<T, 3, TNT>(ta.t, op, cf); break;
-            default: apply_lds<T, 4, TNT>(ta.t, op, cf); break;
+            case 1: apply_lds<T, 1, TNT>(ta.t, op, cf, addr); break;
+            case 2: apply_lds<T, 2, TNT>(ta.t, op, cf, addr); break;
+            case 3: apply_lds<T, 3, TNT>(ta.t, op, cf, addr); break;
+            default: apply_lds<T, 4, TNT>(ta.t, op, cf, addr); break;
             }
         } else {
             // the same on every lane: keeps the loop (and the record
             // addresses) uniform
             status = __builtin_amdgcn_readfirstlane(lds_measure<T, TNT>(ta.t, op, ma, b));
+        }
+        if (i + 1 < nrec) {
+            op = decode_op(rec_at + uint32_t(i + 1) * uint32_t(sizeof(DevOp)));
+            if (op.kind == qs::DEVOP_MAT) prep_addr<T>(op, addr);
         }
         __syncthreads();
         if (status) break;
