@@ -33,9 +33,9 @@ HBM_PEAK_GBS = 8000.0
 # The figures hold for the kernel source with the hash below; for any other
 # source the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "kernels_sha256_16": "c04b72001477edcd",
-    "complex128": (16573.7 * 2.0 + 32768.0) * 1024,
-    "complex64": (8328.5 * 2.0 + 16384.0) * 1024,
+    "kernels_sha256_16": "89f0e3f39f04d3cb",
+    "complex128": (16555.7 * 2.0 + 32777.8) * 1024,
+    "complex64": (8330.6 * 2.0 + 16386.0) * 1024,
 }
 
 
@@ -313,7 +313,8 @@ def main():
             res["avg_launch_us"] = avg_ms * 1e3
             res["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dtype),
-                               "kernel": f"k_tile<{'double' if elem == 16 else 'float'}, LE, 512>",
+                               "kernel": f"k_tile<{'double' if elem == 16 else 'float'}, LE, "
+                                         f"{os.environ.get('QSIM_TILE_THREADS') or (256 if elem == 16 else 512)}>",
                                "bytes_per_launch": pass_bytes, "launches_per_step": launches}
             # one more step with an event pair around every pass: pure kernel
             # time per launch (what a kernel trace reports)
