@@ -160,12 +160,18 @@ def run_batched(qsim, W, n_circuits=4096, n_exp=500, sample_one_at_a_time=48):
             "max_rel_dexpval_vs_c128": float(max(diffs))}
 
 
-def run_served(qsim, W, n_requests=48, load=0.8, wmax=30):
+def run_served(qsim, W, n_requests=48, loads=(0.5, 0.8, 1.0), wmax=30, n_compare=16, wcompare=24):
     """Serving form: requests with log-uniform widths 12..wmax and depths
-    10^3..10^5 gates of the Pauli-exponential style, complex64; first all at
-    once (capacity), then Poisson arrivals at `load` x capacity."""
+    10^3..10^5 gates of the Pauli-exponential style, complex64, 8 slots, pool
+    admission by state bytes.  First a closed-loop run (all requests at once)
+    calibrates capacity; then Poisson arrivals at each offered load x capacity,
+    each on its own request set; latency is completion - arrival.  Last, on
+    requests of width <= wcompare, the served complex64 path against the plain
+    one-circuit-at-a-time complex128 path on the same requests."""
     import numpy as np
-    reqs = W.serving_requests(2 * n_requests, 12, wmax, rate=1.0, seed=8)
+    import torch
+    nsets = 1 + len(loads)
+    reqs = W.serving_requests(nsets * n_requests, 12, wmax, rate=1.0, seed=8)
     circuits = [(r["width"], W.request_circuit(r), W.pauli_sum(r["width"], 20, seed=r["seed"])) for r in reqs]
 
     def serve(batch, arrivals):
@@ -188,41 +194,87 @@ def run_served(qsim, W, n_requests=48, load=0.8, wmax=30):
         span = max(r["t_done"] for r in done.values()) - t0
         bad = sum(1 for r in done.values() if r["status"] != 0)
         return {"circuits_per_s": len(done) / span, "p50_s": pct(lat, 50), "p99_s": pct(lat, 99),
-                "failed": bad, "pool_peak_bytes": st["pool_peak"]}
+                "failed": bad, "pool_peak_bytes": st["pool_peak"]}, {i: done[i] for i in done}
 
-    cap = serve(circuits[:n_requests], [0.0] * n_requests)
-    rate = load * cap["circuits_per_s"]
-    gaps = np.random.default_rng(9).exponential(1.0 / rate, size=n_requests)
-    pois = serve(circuits[n_requests:], list(np.cumsum(gaps)))
+    cap, _ = serve(circuits[:n_requests], [0.0] * n_requests)
+    rng = np.random.default_rng(9)
+    runs = []
+    for j, load in enumerate(loads):
+        rate = load * cap["circuits_per_s"]
+        gaps = rng.exponential(1.0 / rate, size=n_requests)
+        batch = circuits[(j + 1) * n_requests:(j + 2) * n_requests]
+        res, _ = serve(batch, list(np.cumsum(gaps)))
+        runs.append(dict(res, load=load, offered_per_s=rate))
+    # served complex64 vs one-at-a-time complex128 on the same small requests
+    small = [c for c in circuits if c[0] <= wcompare][:n_compare]
+    served_small, got = serve(small, [0.0] * len(small))
+    t0 = time.perf_counter()
+    e128 = []
+    for (w, g, H) in small:
+        prog = qsim.Program(w, g, "complex128")
+        sv = qsim.StateVector(w, "complex128")
+        prog.qsim_run(sv)
+        e128.append(sv.qsim_expval(H))
+        prog.close()
+        sv.close()
+    torch.cuda.synchronize()
+    one_s = time.perf_counter() - t0
+    e64 = [got[i]["expval"] for i in sorted(got)]
+    scale = [float(np.abs(H["coeff"]).sum()) for (_, _, H) in small]
+    dmax = max(abs(a - b) / sc for a, b, sc in zip(e64, e128, scale))
     widths = [c[0] for c in circuits]
     depths = [len(c[1]) for c in circuits]
-    return {"workload": f"{2 * n_requests} requests, widths log-U[12,{wmax}] (max {max(widths)}), depths "
-                        f"{min(depths)}..{max(depths)} gates, complex64, 8 slots, HBM-byte admission",
-            "capacity": cap, "poisson": dict(pois, offered_per_s=rate)}
+    return {"workload": f"{nsets} sets of {n_requests} requests, widths log-U[12,{wmax}] (max {max(widths)}), "
+                        f"depths {min(depths)}..{max(depths)} gates, complex64, 8 slots, HBM-byte admission",
+            "capacity": cap, "poisson": runs,
+            "vs_one_at_a_time_c128": {"requests": len(small), "max_width": max(c[0] for c in small),
+                                      "served_c64_circuits_per_s": served_small["circuits_per_s"],
+                                      "one_at_a_time_c128_circuits_per_s": len(small) / one_s,
+                                      "speedup": served_small["circuits_per_s"] / (len(small) / one_s),
+                                      "max_dexpval_over_sum_abs_c": dmax}}
 
 
-def run_wide_job(qsim, W, n=30, n_exp=8000):
-    """One 30-qubit complex64 job (8 GiB state, HBM-bound passes)."""
+def run_wide_job(qsim, W, n=30, n_exp=40000):
+    """One 30-qubit complex64 job (8 GiB state, HBM-bound passes): about
+    10^4 tile passes.  Beside HBM peak, the rate of a plain device copy of the
+    same footprint (read 8 GiB, write 8 GiB) is reported as a ceiling, timed
+    before and after the job (the job runs for tens of seconds)."""
     import torch
     g, _, _ = W.pauli_exponential_circuit(n, n_exp, seed=31)
     prog = qsim.Program(n, g, "complex64")
     st = prog.qsim_program_stats()
     sv = qsim.StateVector(n, "complex64")
+    src = sv.tensor.view(torch.int64)
+    dst = torch.empty_like(src)
+
+    def copy_rate():
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        return 2 * src.numel() * src.element_size() / ((time.perf_counter() - c0) / 3) / 1e9
+
+    copy_before = copy_rate()
+    sv.qsim_init_zero()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    prog.qsim_run_timed(sv)
+    prog.qsim_run(sv)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ms, launches = prog.qsim_program_kernel_ms()
     nrm = sv.qsim_norm()
+    copy_after = copy_rate()
     prog.close()
+    del dst
     sv.close()
     pass_bytes = 2 * 8 * (1 << n)
-    gbs = pass_bytes / (ms * 1e-3 / launches) / 1e9
+    gbs = pass_bytes * st["passes"] / dt / 1e9
     return {"workload": f"{n} qubits, {n_exp} exponentials ({st['input_gates']} gates), complex64",
-            "passes": st["passes"], "seconds": dt, "gates_per_s": st["input_gates"] / dt,
-            "avg_pass_ms": ms / launches, "pass_GBps": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
-            "norm": nrm}
+            "passes": st["passes"], "tile_qubits": st["tile_qubits"], "seconds": dt,
+            "gates_per_s": st["input_gates"] / dt, "avg_pass_ms": 1e3 * dt / st["passes"], "pass_GBps": gbs,
+            "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "copy_GBps_before": copy_before,
+            "copy_GBps_after": copy_after, "frac_of_copy_before": gbs / copy_before, "norm": nrm}
 
 
 def main():

@@ -49,7 +49,11 @@ void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc
     fc->sparse = true;
     fc->max_params = 0;
     pc->one_op_per_pass = false;
-    pc->tile_qubits = env_int("QSIM_TILE_QUBITS", 12);
+    // 12-qubit tiles while a state gives each CU at most a few of them; for
+    // complex64 states of 23+ qubits (several tiles queued per CU, so loads,
+    // operators and stores of different tiles overlap) 13-qubit tiles, whose
+    // passes carry more operators
+    pc->tile_qubits = env_int("QSIM_TILE_QUBITS", (dtype == QSIM_C64 && n >= 23) ? 13 : 12);
     pc->low_qubits = env_int("QSIM_LOW_QUBITS", dtype == QSIM_C64 ? 4 : 3);
     pc->window = env_int("QSIM_PLAN_WINDOW", 1024);
     pc->max_tile_k = 4;
@@ -808,7 +812,7 @@ int qsim_autotune(qsim_h h, const qsim_gate *g, size_t ng, const double *mats, c
     // the prefix ends at a whole number of records; barriers are kept
     const size_t np = std::min(ng, prefix_gates);
     std::vector<qsim_fuse_opts> cands;
-    const int tdef = 12;
+    const int tdef = (h->dtype == QSIM_C64 && h->n >= 23) ? 13 : 12;
     const int ldef = h->dtype == QSIM_C64 ? 4 : 3;
     const int wmax = h->dtype == QSIM_C64 ? 5 : 4;
     for (int t : {tdef - 1, tdef, tdef + 1}) {
