@@ -234,6 +234,70 @@ def run_served(qsim, W, n_requests=48, loads=(0.5, 0.8, 1.0), wmax=30, n_compare
                                       "max_dexpval_over_sum_abs_c": dmax}}
 
 
+def run_mma(qsim, W, n_sys=20, steps=8, shots=1024, delta=0.3, dtype="complex128"):
+    """Measurement assertion (Section 4.3) against shot-by-shot measurement,
+    on the projection-filter workload (one ancilla, n_sys system qubits,
+    synthetic diagonal Hamiltonian, t_i = t_(i-1)/2).
+
+    MMA: one state; after each step the ancilla is asserted to 0 (its
+    probability tracked) and reset; then all shots are drawn from the final
+    state at once.  Shot by shot: `shots` trajectories in one batch, the
+    ancilla measured with a draw after every step; a shot succeeds when every
+    outcome is 0.  In the shape of the paper's Table 6, the report gives, per
+    step, the asserted probability against the observed rate among the shots
+    still successful."""
+    import numpy as np
+    import torch
+    ga, info = W.projection_filter(n_sys, steps, seed=12, record="assert", delta=delta)
+    gm, _ = W.projection_filter(n_sys, steps, seed=12, record="measure", delta=delta)
+    n = info["n"]
+    cuts = [i for i in range(len(ga)) if ga["kind"][i] == W.KIND_ASSERT0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sv = qsim.StateVector(n, dtype)
+    p_steps = []
+    prev = 0
+    for c in cuts:
+        sv.qsim_apply(ga[prev:c])
+        p_steps.append(sv.qsim_measure_assert(0))
+        sv.qsim_reset(0)
+        prev = c + 2
+    drawn = sv.qsim_sample(W.uniforms(shots, seed=13))
+    torch.cuda.synchronize()
+    t_mma = time.perf_counter() - t0
+    sv.close()
+    b = qsim.Batch([{"n": n, "n_states": shots, "gates": gm, "uniforms": W.uniforms((shots, steps), seed=14),
+                     "n_slots": steps}], dtype=dtype)
+    b.qsim_batch_run()                       # warm-up (and graph-free)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.qsim_batch_run()
+    torch.cuda.synchronize()
+    t_shots = time.perf_counter() - t0
+    res = b.qsim_batch_results(0)
+    b.close()
+    outc = res["outcomes"]
+    alive = np.ones(shots, dtype=bool)
+    table = []
+    for i in range(steps):
+        at_risk = int(alive.sum())
+        zeros = int((alive & (outc[:, i] == 0)).sum())
+        table.append({"step": i + 1, "asserted_p": p_steps[i], "shots_at_risk": at_risk,
+                      "observed_zero": zeros, "expected_zero": at_risk * p_steps[i]})
+        alive &= outc[:, i] == 0
+    ptrack = float(np.prod(p_steps))
+    k = int(alive.sum())
+    sd = (shots * ptrack * (1 - ptrack)) ** 0.5
+    return {"workload": f"projection filter, {n} qubits ({n_sys} system + 1 ancilla), {steps} steps, "
+                        f"delta={delta}, {dtype}, {shots} shots",
+            "mma": {"seconds": t_mma, "tracked_probability": ptrack, "shots_drawn": int(len(drawn)),
+                    "ancilla_zero_in_all_drawn": bool((np.asarray(drawn) & 1 == 0).all())},
+            "shot_by_shot": {"seconds": t_shots, "successful": k, "expected": shots * ptrack,
+                             "z": (k - shots * ptrack) / sd if sd > 0 else 0.0,
+                             "failed_status": int((res["status"] != 0).sum())},
+            "speedup_mma_vs_shots": t_shots / t_mma, "per_step": table}
+
+
 def run_wide_job(qsim, W, n=30, n_exp=40000):
     """One 30-qubit complex64 job (8 GiB state, HBM-bound passes): about
     10^4 tile passes.  Beside HBM peak, the rate of a plain device copy of the
@@ -292,7 +356,7 @@ def main():
                     help="first run a plain 256 MiB device copy five times (a known byte count for "
                          "scaling memory counters)")
     ap.add_argument("--forms", default="", help="comma list of extra forms to run: "
-                    "trajectories,batched,served,wide (or 'all')")
+                    "trajectories,batched,served,mma,wide (or 'all')")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); "
@@ -389,9 +453,9 @@ def main():
     forms = {}
     want = set(args.forms.split(",")) if args.forms else set()
     if "all" in want:
-        want = {"trajectories", "batched", "served", "wide"}
+        want = {"trajectories", "batched", "served", "mma", "wide"}
     for name, fn in (("trajectories", run_trajectories), ("batched", run_batched),
-                     ("served", run_served), ("wide", run_wide_job)):
+                     ("served", run_served), ("mma", run_mma), ("wide", run_wide_job)):
         if name in want:
             log(f"[bench] form: {name}")
             forms[name] = fn(qsim, W)

@@ -23,6 +23,10 @@ def Q():
     return qsim
 
 
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
 def filter_steps(n_sys, steps, seed):
     """Trial state of Ry rotations; each step exp[-i (H t + delta) Y_a] with a
     diagonal H = h0 + sum_j h_j Z_j on the system qubits 1..n_sys."""
@@ -71,3 +75,47 @@ def test_assertion_chain_and_sampling(Q, dtype, n_sys):
     assert len(mism) <= (0 if dtype == "complex128" else 40)
     # the ancilla is |0> in every shot
     assert (shots & 1 == 0).all()
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+def test_shots_reproduce_asserted_probability(Q, dtype):
+    """The projection filter run shot by shot (the ancilla measured with a
+    draw after every step, then reset) succeeds -- every outcome 0 -- at the
+    rate the assertion chain tracks: P(all 0) = prod_i p_i (Section 4.3).
+    4096 trajectories in one batch, against one asserted state."""
+    n_sys, steps, ntraj = 10, 5, 4096
+    # delta = 0.3 keeps the success rate near 0.44, where the count is most
+    # sensitive to a wrong probability
+    ga, info = W.projection_filter(n_sys, steps, seed=31, record="assert", delta=0.3)
+    gm, _ = W.projection_filter(n_sys, steps, seed=31, record="measure", delta=0.3)
+    n = info["n"]
+    sv = Q.StateVector(n, dtype)
+    ptrack = 1.0
+    g_prev = 0
+    # the asserted chain, one step at a time through the ABI
+    rec_kinds = ga["kind"]
+    cuts = [i for i in range(len(ga)) if rec_kinds[i] == W.KIND_ASSERT0]
+    p_steps = []
+    for c in cuts:
+        sv.qsim_apply(ga[g_prev:c])
+        p = sv.qsim_measure_assert(0)
+        p_steps.append(p)
+        ptrack *= p
+        sv.qsim_reset(0)
+        g_prev = c + 2          # skip the ASSERT0 and RESET records
+    _, _, want_p = oracle.run(n, ga)
+    tol = 1e-12 if dtype == "complex128" else 1e-5
+    np.testing.assert_allclose(p_steps, want_p, atol=tol)
+    u = W.uniforms((ntraj, steps), seed=32)
+    say("shots vs assertion", dtype)
+    b = Q.Batch([{"n": n, "n_states": ntraj, "gates": gm, "uniforms": u, "n_slots": steps}], dtype=dtype)
+    b.qsim_batch_run()
+    res = b.qsim_batch_results(0)
+    assert (res["status"] == 0).all()
+    ok = (res["outcomes"] == 0).all(axis=1)
+    k = int(ok.sum())
+    mean = ntraj * ptrack
+    sd = math.sqrt(ntraj * ptrack * (1 - ptrack))
+    assert abs(k - mean) <= 4.5 * sd, (k, mean, sd)
+    # along every successful trajectory each step saw the asserted p_i
+    np.testing.assert_allclose(res["probs"][ok], np.broadcast_to(want_p, (k, steps)), atol=max(tol, 1e-12) * 10)

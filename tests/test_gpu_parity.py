@@ -217,6 +217,22 @@ def test_cfg2_full_width_prefix(Q, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+def test_wide_state_default_tiles(Q, dtype):
+    """23 qubits with the default options: complex64 takes 13-qubit tiles
+    from 23 qubits up (several tiles per CU), complex128 12-qubit tiles."""
+    n = 23
+    g, _, _ = W.pauli_exponential_circuit(n, 60, seed=23)
+    H = W.pauli_sum(n, 30, seed=24)
+    say("wide default tiles", dtype)
+    sv = run_gpu(Q, n, g, dtype)
+    st = sv.qsim_last_stats()
+    assert st["tile_qubits"] == (13 if dtype == "complex64" else 12)
+    want, _, _ = oracle.run(n, g)
+    check_state(sv.qsim_get_state(), want, dtype)
+    assert abs(sv.qsim_expval(H) - oracle.expval(n, want, H)) <= 1e-6 * np.abs(H["coeff"]).sum()
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
 def test_cfg2_full_circuit_inverse_property(Q, dtype):
     """The full benchmark circuit (50,000 exponentials, 21 qubits) followed
     by its inverse returns |0...0>: a property that holds at any size."""

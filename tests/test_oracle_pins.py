@@ -364,6 +364,32 @@ def test_projection_filter_closed_form():
     assert np.allclose(psi.reshape(1 << m, 2)[:, 1], 0)
 
 
+def test_projection_filter_generator_closed_form():
+    """The projection-filter workload generator (qubit 0 the ancilla, synthetic
+    diagonal H, t_i = t_{i-1}/2) builds the circuit of Eq. (proj): the oracle's
+    tracked probability after N asserted steps equals
+    sum_x |C_x|^2 prod_i cos^2(E_x t_i), with C_x from the generator's Ry
+    angles and E_x = h0 + sum_j h_j z_j(x); the same circuit with measurement
+    records forced to 0 gives the same per-step probabilities."""
+    g, info = W.projection_filter(5, 4, seed=7, record="assert")
+    h0, h, ts, n = info["h0"], info["h"], info["t"], info["n"]
+    m = len(h)
+    phis = [float(r["theta"][0]) for r in g[:m]]
+    assert [int(r["q"][0]) for r in g[:m]] == list(range(1, m + 1))
+    E = np.array([h0 + sum(h[j] * (1 - 2 * ((x >> j) & 1)) for j in range(m)) for x in range(1 << m)])
+    C = np.array([np.prod([math.cos(phis[j] / 2) if not (x >> j) & 1 else math.sin(phis[j] / 2)
+                           for j in range(m)]) for x in range(1 << m)])
+    filt = np.prod([np.cos(E * t) for t in ts], axis=0)
+    psi, _, probs = oracle.run(n, g)
+    assert abs(np.prod(probs) - np.sum(np.abs(C * filt) ** 2)) < 1e-13
+    assert abs(ts[0] - math.pi / (4 * np.abs(h).sum())) < 1e-15 and all(
+        abs(ts[i + 1] - ts[i] / 2) < 1e-15 for i in range(len(ts) - 1))
+    gm, _ = W.projection_filter(5, 4, seed=7, record="measure")
+    _, outc, pm = oracle.run(n, gm, forced=np.zeros(4, dtype=np.int32))
+    assert (outc == 0).all()
+    np.testing.assert_allclose(pm, probs, rtol=0, atol=1e-14)
+
+
 def _golden_table6():
     import os
     path = os.path.join(os.path.dirname(__file__), "golden", "table6_mma.txt")

@@ -282,6 +282,38 @@ def trajectory_round_program(n_sys: int = 12, rounds: int = 500, seed: int = 4):
     return gates(recs)
 
 
+def projection_filter(n_sys: int = 20, n_steps: int = 8, seed: int = 12, record: str = "assert",
+                      t1: float = None, delta: float = 0.0):
+    """Projection-filter workload on one ancilla (qubit 0) and n_sys system
+    qubits (1..n_sys), with a synthetic diagonal Hamiltonian
+    H = h0 + sum_j h_j Z_j (h0 = 0.1, h_j ~ N(0, 0.6^2)) standing in for the
+    paper's nuclear Hamiltonians.  The trial state is a product of Ry(U[0, pi))
+    rotations.  Step i applies exp[-i (H t_i + delta) Y_a], compiled as
+    Ry_a(2 (t_i h0 + delta)) and, for every system qubit j, the exponential of
+    t_i h_j Z_j Y_a (the two commute term by term because H is diagonal), with
+    t_1 = pi / (2 Delta) (Delta = 2 sum |h_j|, the spectral width) unless given
+    and t_i = t_(i-1) / 2.  After each step the ancilla is measured
+    (record="measure", slot i) or asserted to 0 (record="assert", slot i),
+    then reset.
+
+    Returns (gates, info) with info = {"h0", "h", "t", "n"}."""
+    rng = _rng(seed)
+    h0 = 0.1
+    h = rng.normal(0.0, 0.6, size=n_sys)
+    if t1 is None:
+        t1 = math.pi / (2.0 * 2.0 * float(np.abs(h).sum()))
+    ts = [t1 / 2 ** i for i in range(n_steps)]
+    recs = [(KIND_RY, (j + 1,), (float(rng.uniform(0, math.pi)),)) for j in range(n_sys)]
+    kind = {"assert": KIND_ASSERT0, "measure": KIND_MEASURE}[record]
+    for i, t in enumerate(ts):
+        recs.append((KIND_RY, (0,), (2.0 * (t * h0 + delta),)))
+        for j in range(n_sys):
+            compile_pauli_exponential(np.array([0, j + 1]), np.array([2, 3]), 2.0 * t * float(h[j]), -1, recs)
+        recs.append((kind, (0,), (), i))
+        recs.append((KIND_RESET, (0,), ()))
+    return gates(recs), {"h0": h0, "h": h, "t": ts, "n": n_sys + 1}
+
+
 def uniforms(shape, seed: int = 5) -> np.ndarray:
     """float64 uniforms in [0, 1) used as measurement draws."""
     return _rng(seed).random(size=shape)
