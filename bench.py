@@ -51,23 +51,42 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n, g, target_s=12.0):
-    """The oracle (FP64, one gate at a time) on a prefix of the circuit."""
-    import numpy as np
+def cpu_baseline(n, g, target_s=12.0, target_1t_s=6.0):
+    """The oracle (FP64, one gate at a time) on a prefix of the circuit, timed
+    on the host's cores with OpenMP over the amplitude loop, then on one
+    thread."""
     import oracle
-    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
-    # calibrate on a short prefix, then time a prefix of about target_s
-    k = 200
-    t0 = time.perf_counter()
-    oracle.run(n, g[:k])
-    dt = time.perf_counter() - t0
-    k2 = int(min(len(g), max(k, k * target_s / max(dt, 1e-3))))
-    t0 = time.perf_counter()
-    oracle.run(n, g[:k2])
-    dt2 = time.perf_counter() - t0
-    return {"value": k2 / dt2, "unit": "gates/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {k2} of {len(g)} gates of the same {n}-qubit circuit, FP64, "
-                      f"{dt2:.1f} s wall, OpenMP over the amplitude loop"}
+
+    def timed(target):
+        # calibrate on a short prefix, then time a prefix of about `target` s
+        k = 100
+        t0 = time.perf_counter()
+        oracle.run(n, g[:k])
+        dt = time.perf_counter() - t0
+        k2 = int(min(len(g), max(k, k * target / max(dt, 1e-3))))
+        t0 = time.perf_counter()
+        oracle.run(n, g[:k2])
+        return k2, time.perf_counter() - t0
+
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    cores = oracle.set_threads(0)
+    k_all, dt_all = timed(target_s)
+    oracle.set_threads(1)
+    k_1, dt_1 = timed(target_1t_s)
+    oracle.set_threads(cores)
+    return {"value": k_all / dt_all, "unit": "gates/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {k_all} of {len(g)} gates of the same {n}-qubit circuit, FP64, "
+                      f"{dt_all:.1f} s wall, OpenMP over the amplitude loop on {cores} threads ({model})",
+            "single_thread": {"value": k_1 / dt_1, "unit": "gates/s", "cores": 1,
+                              "sample": f"first {k_1} gates, {dt_1:.1f} s wall"}}
 
 
 def pct(xs, q):

@@ -72,12 +72,20 @@ def _load():
         lib.orc_expval.argtypes = [C.c_int, P, P, C.c_int64]
         lib.orc_expval.restype = C.c_double
         lib.orc_gate_matrix.argtypes = [P, P, P]
+        lib.orc_set_threads.argtypes = [C.c_int]
+        lib.orc_set_threads.restype = C.c_int
         _lib = lib
     return _lib
 
 
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def set_threads(k: int = 0) -> int:
+    """OpenMP threads of the amplitude loops (0: leave as is); returns the
+    number in effect.  For timing only: results do not depend on it."""
+    return _load().orc_set_threads(int(k))
 
 
 def zero_state(n: int) -> np.ndarray:

@@ -16,6 +16,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -464,4 +465,12 @@ double orc_expval(int n, const double *psi, const orc_pauli *t, int64_t nt) {
         total += t[k].coeff * creal(acc);
     }
     return total / orc_norm(n, psi);
+}
+
+/* Threads used by the amplitude loops (timing runs only: every loop sums in
+ * a fixed order per amplitude, so the results do not depend on it).  Returns
+ * the number now in effect. */
+int orc_set_threads(int k) {
+    if (k > 0) omp_set_num_threads(k);
+    return omp_get_max_threads();
 }
