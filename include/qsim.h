@@ -381,6 +381,30 @@ int qsim_debug_fuse(int n, const qsim_gate *g, size_t ng, const double *mats,
                     size_t cap_ops, size_t cap_doubles, size_t *n_ops,
                     int64_t *counts);
 
+/* Parse an OpenQASM 2.0 program into gate records (host only; the paper
+ * ingests its circuits as QASM text, Section 4.1, with the gate set of its
+ * Table 3).
+ *
+ * text, len: the program (not necessarily NUL-terminated).  Qubits and
+ * classical bits are numbered across their registers in declaration order
+ * (n_qubits, n_clbits receive the totals; either may be NULL).  Accepted: the
+ * OPENQASM header; include lines (the standard gates are built in: id h x y z
+ * s sdg t tdg sx rx ry rz u1 p u2 u3 u U cx CX cy cz ch swap crx cry crz cu1
+ * cp cu3 rxx rzz ccx cswap c3x c3sqrtx c4x); qreg / creg; gate definitions
+ * with parameters (expanded at each call); calls on qubits or whole registers
+ * (broadcast over equal sizes); measure (record MEASURE, slot = classical bit
+ * index), reset, barrier; parameter expressions with pi, + - * / ^, unary
+ * minus, parentheses, sin cos tan exp ln sqrt.
+ *
+ * out: caller array of cap records (may be NULL with cap 0 to size the
+ * output); *n_out always receives the number of records of the program.
+ * Errors: QSIM_E_CAPACITY when cap < *n_out (nothing written); QSIM_E_ARG on
+ * a syntax error or a wrong operand count, QSIM_E_QUBIT on an out-of-range
+ * index or a repeated qubit, QSIM_E_UNSUPPORTED on if, opaque or an unknown
+ * gate -- qsim_last_error() then names the line. */
+int qsim_parse_qasm(const char *text, size_t len, qsim_gate *out, size_t cap, size_t *n_out,
+                    int32_t *n_qubits, int32_t *n_clbits);
+
 /* Host-only: number of full-state passes the planner makes for the fused
  * circuit (same inputs as qsim_debug_fuse), for n qubits and dtype. */
 int qsim_debug_plan(int n, int dtype, const qsim_gate *g, size_t ng,

@@ -905,6 +905,30 @@ int qsim_debug_fuse(int n, const qsim_gate *g, size_t ng, const double *mats, co
     return QSIM_OK;
 }
 
+int qsim_parse_qasm(const char *text, size_t len, qsim_gate *out, size_t cap, size_t *n_out,
+                    int32_t *n_qubits, int32_t *n_clbits) {
+    if ((!text && len) || !n_out) return QSIM_E_ARG;
+    std::vector<qsim_gate> g;
+    int nq = 0, nc = 0;
+    std::string err;
+    int rc;
+    try {
+        rc = parse_qasm(text ? text : "", len, &g, &nq, &nc, &err);
+    } catch (const std::bad_alloc &) {
+        return QSIM_E_NOMEM;
+    }
+    if (rc) {
+        std::snprintf(g_last_error, sizeof(g_last_error), "%s", err.c_str());
+        return rc;
+    }
+    *n_out = g.size();
+    if (n_qubits) *n_qubits = nq;
+    if (n_clbits) *n_clbits = nc;
+    if (g.size() > cap || (!out && !g.empty())) return QSIM_E_CAPACITY;
+    if (!g.empty()) std::memcpy(out, g.data(), g.size() * sizeof(qsim_gate));
+    return QSIM_OK;
+}
+
 int qsim_debug_plan(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
                     const double *params, const qsim_fuse_opts *opt, qsim_apply_stats *out) {
     if (n < 1 || n > kMaxQubits || (dtype != QSIM_C64 && dtype != QSIM_C128) || !out) return QSIM_E_ARG;

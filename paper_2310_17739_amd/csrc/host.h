@@ -69,6 +69,12 @@ struct FuseConfig {
     bool sparse = true;
 };
 
+// ---- OpenQASM 2.0 frontend (qasm.cpp)
+// Parses the program into gate records; on error returns the status and a
+// message naming the line in *err.
+int parse_qasm(const char *text, size_t len, std::vector<qsim_gate> *out, int *n_qubits, int *n_clbits,
+               std::string *err);
+
 // ---- lowering (gates.cpp)
 // Returns QSIM_OK or an error; fills `out`.  Gate matrices are built in FP64.
 // Measurement records are accepted only with `allow_meas`.

@@ -86,6 +86,7 @@ def _load():
         "qsim_get_state": ([P, P], I),
         "qsim_set_state": ([P, P], I),
         "qsim_debug_fuse": ([I, P, SZ, P, P, P, P, P, P, SZ, SZ, P, P], I),
+        "qsim_parse_qasm": ([C.c_char_p, SZ, P, SZ, P, P, P], I),
         "qsim_compile": ([I, I, P, SZ, P, P, P, P], I),
         "qsim_run": ([P, P], I),
         "qsim_program_graph": ([P, P, I], I),
@@ -563,6 +564,24 @@ def qsim_debug_fuse(n, gates, mats=None, params=None, level=5, max_width=4, flag
         pos += 2 * d * d
         ops.append((list(out_q[5 * i:5 * i + k]), mat))
     return ops, counts
+
+
+def qsim_parse_qasm(text):
+    """OpenQASM 2.0 text -> (gate records, n_qubits, n_clbits)."""
+    b = text.encode() if isinstance(text, str) else bytes(text)
+    n_out, nq, nc = C.c_size_t(), C.c_int32(), C.c_int32()
+    # one record per statement unless broadcasts or gate definitions expand:
+    # then the first call reports the size and a second one fills it
+    out = np.zeros(max(b.count(b";"), 1), dtype=GATE_DTYPE)
+    for _ in range(2):
+        rc = _lib.qsim_parse_qasm(b, len(b), _p(out), len(out), C.byref(n_out), C.byref(nq), C.byref(nc))
+        if rc == E_CAPACITY:
+            out = np.zeros(n_out.value, dtype=GATE_DTYPE)
+            continue
+        if rc != OK:
+            raise QsimError(rc, "qsim_parse_qasm: " + _lib.qsim_last_error().decode())
+        return out[:n_out.value], nq.value, nc.value
+    check(rc, "qsim_parse_qasm")
 
 
 def qsim_debug_plan(n, gates, dtype="complex128", mats=None, params=None, level=None,

@@ -390,6 +390,38 @@ def random_state(n: int, seed: int) -> np.ndarray:
     return v / np.linalg.norm(v)
 
 
+QASM_NAMES = {
+    KIND_ID: "id", KIND_H: "h", KIND_X: "x", KIND_Y: "y", KIND_Z: "z", KIND_S: "s", KIND_SDG: "sdg",
+    KIND_T: "t", KIND_TDG: "tdg", KIND_SX: "sx", KIND_RX: "rx", KIND_RY: "ry", KIND_RZ: "rz",
+    KIND_U1: "u1", KIND_U2: "u2", KIND_U3: "u3", KIND_CX: "cx", KIND_CY: "cy", KIND_CZ: "cz",
+    KIND_CH: "ch", KIND_SWAP: "swap", KIND_CRX: "crx", KIND_CRY: "cry", KIND_CRZ: "crz",
+    KIND_CU1: "cu1", KIND_CU3: "cu3", KIND_RXX: "rxx", KIND_RZZ: "rzz", KIND_CCX: "ccx",
+    KIND_CSWAP: "cswap", KIND_C3X: "c3x", KIND_C3XSQRTX: "c3sqrtx", KIND_C4X: "c4x",
+}
+
+
+def to_qasm(g: np.ndarray, n: int, n_clbits: int = 0) -> str:
+    """OpenQASM 2.0 text of gate records (one qreg q[n], one creg c[n_clbits]
+    when measurements occur; angles printed with 17 significant digits)."""
+    lines = ["OPENQASM 2.0;", 'include "qelib1.inc";', f"qreg q[{n}];"]
+    if n_clbits:
+        lines.append(f"creg c[{n_clbits}];")
+    for r in g:
+        k = int(r["kind"])
+        qs = ", ".join(f"q[{int(x)}]" for x in r["q"][:int(r["nq"])])
+        if k == KIND_BARRIER:
+            lines.append(f"barrier q;")
+        elif k == KIND_MEASURE:
+            lines.append(f"measure q[{int(r['q'][0])}] -> c[{int(r['slot'])}];")
+        elif k == KIND_RESET:
+            lines.append(f"reset q[{int(r['q'][0])}];")
+        else:
+            npar = KIND_NPARAMS.get(k, 0)
+            par = "(" + ", ".join(repr(float(x)) for x in r["theta"][:npar]) + ")" if npar else ""
+            lines.append(f"{QASM_NAMES[k]}{par} {qs};")
+    return "\n".join(lines) + "\n"
+
+
 def inverse_circuit(g: np.ndarray) -> np.ndarray:
     """The gate list of the inverse of a circuit made of self-inverse gates
     (H, X, Y, Z, CX, CY, CZ, SWAP) and rotations (angle negated): records in
