@@ -119,7 +119,10 @@ typedef struct qsim_fuse_opts {
 
 enum {
     QSIM_F_ONE_OP_PER_PASS = 1,  /* every fused operator is its own full-state sweep */
-    QSIM_F_NO_SPARSE = 2         /* treat fused operators as dense (no zero skipping) */
+    QSIM_F_NO_SPARSE = 2,        /* treat fused operators as dense (no zero skipping) */
+    QSIM_F_FULL_SUPPORT = 4      /* keep every qubit of an operator in its LDS tile
+                                    (default: qubits on which the operator is
+                                    diagonal may stay outside the tile) */
 };
 
 /* Counters of the last qsim_apply (host-side compile and device plan). */

@@ -67,6 +67,7 @@ void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc
         if (opt->low_qubits > 0) pc->low_qubits = opt->low_qubits;
         pc->one_op_per_pass = (opt->flags & QSIM_F_ONE_OP_PER_PASS) != 0;
         fc->sparse = (opt->flags & QSIM_F_NO_SPARSE) == 0;
+        pc->full_support = (opt->flags & QSIM_F_FULL_SUPPORT) != 0;
     }
     if (dtype == QSIM_C128) fc->max_width = std::min(fc->max_width, 4);
     fc->max_width = std::max(1, std::min(fc->max_width, kMaxK));
@@ -137,18 +138,25 @@ int validate_plan(int n, int dtype, const Compiled &c) {
                 if (pi.strided || pi.ta.t != n || o.pos[0] >= n || o.kind > DEVOP_RESET) return QSIM_E_ARG;
                 continue;
             }
-            if (o.k < 1 || o.k > kMaxK || o.k > width) return QSIM_E_ARG;
+            // tiled passes may hold operators with block qubits (kx > 0),
+            // which must lie outside the tile; k = 0 then is an operator
+            // diagonal on all its qubits
+            if (pi.strided ? (o.kx != 0 || o.k < 1) : (o.k + o.kx < 1)) return QSIM_E_ARG;
+            if (o.k > width || o.k + o.kx > kMaxK) return QSIM_E_ARG;
             if (!pi.strided && o.k > 4) return QSIM_E_ARG;
             for (int a = 0; a < o.k; a++) {
                 if (o.pos[a] >= width) return QSIM_E_ARG;
                 if (a && o.pos[a] <= o.pos[a - 1]) return QSIM_E_ARG;
                 if (!pi.strided && o.slot[a] != lds_slot(int(elem_bytes(dtype)), 1 << o.pos[a])) return QSIM_E_ARG;
             }
+            for (int a = 0; a < o.kx; a++) {
+                if (o.xq[a] >= n || ((pi.ta.tile_mask >> o.xq[a]) & 1)) return QSIM_E_ARG;
+                if (a && o.xq[a] <= o.xq[a - 1]) return QSIM_E_ARG;
+            }
             const uint32_t d = 1u << o.k;
             const uint32_t mask = (d >= 32) ? 0xffffffffu : ((1u << d) - 1);
             if (!o.present || (o.present & ~mask)) return QSIM_E_ARG;
-            const size_t need = size_t(o.coef) + size_t(__builtin_popcount(o.present)) * d *
-                                                     (size_t(1) << p.op_np[j]);
+            const size_t need = size_t(o.coef) + size_t(devop_coefs(o)) * (size_t(1) << p.op_np[j]);
             if (need > p.coefs.size()) return QSIM_E_ARG;
             if (!pi.strided && (o.coef < p.coef_begin[i] || need > p.coef_begin[i + 1])) return QSIM_E_ARG;
             if (p.op_np[j] < 0 || p.op_np[j] > 3) return QSIM_E_ARG;
@@ -182,9 +190,13 @@ int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const doubl
         meta[i] = uint32_t(sizeof(DevOp) + size_t(__builtin_popcount(present[i])) *
                                                L.ops[i].dim() * elem_bytes(dtype));
     }
+    std::vector<uint64_t> need(L.ops.size());
+    for (size_t i = 0; i < L.ops.size(); i++)
+        need[i] = pc.full_support ? L.ops[i].mask() : op_moved_qubits(L.ops[i], present[i]);
     std::vector<Pass> passes;
-    plan_passes(n, L, meta, pc, &passes);
-    pack_plan(L.ops, present, passes, &out->plan);
+    plan_passes(n, L, meta, need, pc, &passes);
+    rc = pack_plan(L.ops, present, passes, &out->plan);
+    if (rc) return rc;
     // LDS slot offsets of the tile positions (the tile kernel's layout)
     for (size_t i = 0; i < passes.size(); i++) {
         if (passes[i].strided || passes[i].kind != Pass::TILE) continue;

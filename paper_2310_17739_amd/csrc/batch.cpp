@@ -119,7 +119,7 @@ size_t bind_layout(Compiled *c, std::vector<qk::BindEntry> *ents, uint32_t *max_
     for (size_t j = 0; j < p.ops.size(); j++) {
         DevOp &o = p.ops[j];
         if (o.kind != DEVOP_MAT) continue;
-        const uint32_t count = uint32_t(__builtin_popcount(o.present)) << o.k;
+        const uint32_t count = devop_coefs(o);
         qk::BindEntry e{};
         e.bound_off = uint32_t(bound);
         e.count = count;
@@ -137,7 +137,7 @@ size_t bind_layout(Compiled *c, std::vector<qk::BindEntry> *ents, uint32_t *max_
     for (size_t i = 0; i + 1 < p.pass_begin.size(); i++) {
         new_begin[i] = uint32_t(run);
         for (uint32_t j = p.pass_begin[i]; j < p.pass_begin[i + 1]; j++)
-            if (p.ops[j].kind == DEVOP_MAT) run += uint32_t(__builtin_popcount(p.ops[j].present)) << p.ops[j].k;
+            if (p.ops[j].kind == DEVOP_MAT) run += devop_coefs(p.ops[j]);
     }
     new_begin.back() = uint32_t(run);
     p.coef_begin = new_begin;

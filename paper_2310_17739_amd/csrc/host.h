@@ -116,28 +116,36 @@ struct PlanConfig {
     size_t meta_budget = 16384;   // bytes of a pass's operator records and coefficients
     int threads = 512;            // tile kernel workgroup size (256 or 512)
     bool one_op_per_pass = false;
+    bool full_support = false;    // every qubit of an operator in its tile
 };
 
 // meta_bytes[i]: LDS bytes operator i needs in a tiled pass (record +
-// coefficients at the state precision).  Measurement records of L.meas are
-// placed between epochs: inside resident passes (t == n) as records, as
-// passes of their own otherwise.
+// coefficients at the state precision); need[i]: the qubits operator i must
+// have inside its tile (all of its qubits, or only those some XOR shift of it
+// moves).  Measurement records of L.meas are placed between epochs: inside
+// resident passes (t == n) as records, as passes of their own otherwise.
 void plan_passes(int n, const Lowered &L, const std::vector<uint32_t> &meta_bytes,
-                 const PlanConfig &cfg, std::vector<Pass> *passes);
+                 const std::vector<uint64_t> &need, const PlanConfig &cfg, std::vector<Pass> *passes);
 
 // ---- packing into device tables (plan.cpp)
 // Device operator record (32 bytes, read as eight scalar words): see kernels.hip.
 struct DevOp {
-    uint32_t coef;     // offset of the first term's coefficients (complex elements)
-    uint32_t present;  // bit m set: the XOR-shift-m diagonal is nonzero
-    uint8_t k;
-    uint8_t pos[5];    // qubit positions (tile-local for tiled passes, global for strided)
+    uint32_t coef;     // offset of the first coefficient (complex elements)
+    uint32_t present;  // bit m set: the XOR-shift-m diagonal over the k positions is nonzero
+    uint8_t k;         // qubits addressed by position (tile-local in tiled passes, global in strided)
+    uint8_t pos[5];    // their positions, ascending
     uint8_t kind;      // DEVOP_*
-    uint8_t pad;
+    uint8_t kx;        // tiled passes: further qubits, outside the tile, on which the operator is diagonal
     uint16_t slot[5];  // tiled passes: LDS slot offset of position j's bit, lds_slot(1 << pos[j])
-    uint16_t pad2[3];
+    uint8_t xq[5];     // their qubit numbers, ascending; bit j of the tile's base index is bit k + j
+                       // of the operator's local index and selects the coefficient block
+    uint8_t pad;
 };
 static_assert(sizeof(DevOp) == 32, "DevOp layout");
+
+// Coefficients of one record: for each of the 2^kx blocks, each present
+// shift's 2^k diagonal entries.
+inline uint32_t devop_coefs(const DevOp &o) { return uint32_t(__builtin_popcount(o.present)) << (o.k + o.kx); }
 
 enum { DEVOP_MAT = 0, DEVOP_MEASURE = 1, DEVOP_ASSERT0 = 2, DEVOP_RESET = 3 };
 
@@ -155,11 +163,16 @@ struct PackedPlan {
 // (all shifts when `sparse` is false).
 uint32_t op_present(const Op &o, bool sparse);
 
-// Pack fused ops into device records following `passes`.  For
-// parameterised ops the coefficient layout holds the 2^np basis blocks
-// (a bind step combines them).
-void pack_plan(const std::vector<Op> &ops, const std::vector<uint32_t> &present,
-               const std::vector<Pass> &passes, PackedPlan *out);
+// Qubits of `o` that some present XOR shift moves (its off-diagonal support).
+uint64_t op_moved_qubits(const Op &o, uint32_t present);
+
+// Pack fused ops into device records following `passes`.  In a tiled pass an
+// operator's qubits outside the tile become its block qubits (kx, xq), which
+// requires it to be diagonal on them.  For parameterised ops the coefficient
+// layout holds the 2^np basis blocks (a bind step combines them).  Returns
+// QSIM_OK, or QSIM_E_ARG if a tiled pass leaves a moved qubit outside its tile.
+int pack_plan(const std::vector<Op> &ops, const std::vector<uint32_t> &present,
+              const std::vector<Pass> &passes, PackedPlan *out);
 
 double now_seconds();
 

@@ -181,9 +181,10 @@ struct LdsTile {
 // Operator record fields, read as eight scalar words (see qs::DevOp).
 struct OpRec {
     uint32_t coef, present;
-    int k, kind;
+    int k, kind, kx;
     int pos[5];
     int slot[5];
+    int xq[5];
 };
 
 // The record at LDS byte address `at` (the same for every lane): eight words,
@@ -205,11 +206,17 @@ __device__ __forceinline__ OpRec decode_op(uint32_t at) {
     o.pos[3] = int(w[3] & 0xff);
     o.pos[4] = int((w[3] >> 8) & 0xff);
     o.kind = int((w[3] >> 16) & 0xff);
+    o.kx = int(w[3] >> 24);
     o.slot[0] = int(w[4] & 0xffff);
     o.slot[1] = int(w[4] >> 16);
     o.slot[2] = int(w[5] & 0xffff);
     o.slot[3] = int(w[5] >> 16);
     o.slot[4] = int(w[6] & 0xffff);
+    o.xq[0] = int((w[6] >> 16) & 0xff);
+    o.xq[1] = int(w[6] >> 24);
+    o.xq[2] = int(w[7] & 0xff);
+    o.xq[3] = int((w[7] >> 8) & 0xff);
+    o.xq[4] = int((w[7] >> 16) & 0xff);
     return o;
 }
 
@@ -265,53 +272,70 @@ __device__ __forceinline__ void prep_addr(const OpRec &op, uint32_t (&addr)[16])
     }
 }
 
-template <typename T, int K, int TNT>
+// One operator on the tile in LDS.  The tile has 2^t = E * TNT elements
+// (E = 2^LE per thread when t > log2 TNT) in 2^(t-K) groups of 2^K.  With
+// K >= LE a thread has at most one group, at addr0.  With K < LE it has
+// 2^(LE-K) groups, tid + i * TNT for i < 2^(LE-K); inserting the operator's
+// zero bits and the LDS fold are both linear, so group i's members sit at
+// addr0[r] ^ gof(i), where gof is the same on every lane.  Up to 16 of a
+// thread's amplitudes are loaded before the first multiply, so that the LDS
+// latency is paid once per batch rather than once per group.
+template <typename T, int K, int LE, int TNT>
 __device__ __forceinline__ void apply_lds(int t, const OpRec &op, uint32_t cfb, const uint32_t (&addr0)[16]) {
     using L = LdsTile<T>;
     constexpr int D = 1 << K;
-    const int ngroups = 1 << (t - K);
-    auto group = [&](const uint32_t (&addr)[D]) {
-        Cx<T> x[D];
-#pragma unroll
-        for (int r = 0; r < D; r++) x[r] = L::ld(addr[r]);
-        // complex128 computes and stores the outputs in chunks of RC when
-        // 512 threads share the CU, to keep 4 waves per SIMD
-        constexpr int RC = (sizeof(T) == 8 && TNT == 512 && D > APPLY_CHUNK_C128) ? APPLY_CHUNK_C128 : D;
+    // complex128 computes and stores the outputs in chunks of RC when 512
+    // threads share the CU, to keep 4 waves per SIMD
+    constexpr int RC = (sizeof(T) == 8 && TNT == 512 && D > APPLY_CHUNK_C128) ? APPLY_CHUNK_C128 : D;
+    auto compute_store = [&](const Cx<T> (&x)[D], uint32_t gofs) {
         static_for<0, D / RC>([&](auto ci) {
             constexpr int R0 = decltype(ci)::value * RC;
             Cx<T> y[RC];
             apply_chunk_lds<T, K, R0, RC>(x, y, op.present, cfb);
 #pragma unroll
-            for (int r = 0; r < RC; r++) L::st(addr[R0 + r], y[r]);
+            for (int r = 0; r < RC; r++) L::st(addr0[R0 + r] ^ gofs, y[r]);
         });
     };
-    if (int(threadIdx.x) < ngroups) {
-        uint32_t addr[D];
+    if constexpr (K >= LE) {
+        if (int(threadIdx.x) < (1 << (t - K))) {
+            Cx<T> x[D];
 #pragma unroll
-        for (int r = 0; r < D; r++) addr[r] = addr0[r];
-        group(addr);
-    }
-    if (ngroups <= TNT) return;
-    // further groups of this thread (operators on fewer qubits)
-    int p[K];
-#pragma unroll
-    for (int j = 0; j < K; j++) p[j] = op.pos[j];
-    uint32_t off[D];
-    off[0] = 0;
-#pragma unroll
-    for (int r = 1; r < D; r++) off[r] = off[r & (r - 1)] ^ (uint32_t(op.slot[__builtin_ctz(r)]) << L::LOGE);
-    for (int g = threadIdx.x + TNT; g < ngroups; g += TNT) {
-        int base = g;
-#pragma unroll
-        for (int j = 0; j < K; j++) base = ((base >> p[j]) << (p[j] + 1)) | (base & ((1 << p[j]) - 1));
-        const uint32_t b0 = uint32_t(sw<T>(base)) << L::LOGE;
-        uint32_t addr[D];
-#pragma unroll
-        for (int r = 0; r < D; r++) {
-            addr[r] = b0 ^ off[r];
-            asm volatile("" : "+v"(addr[r]));
+            for (int r = 0; r < D; r++) x[r] = L::ld(addr0[r]);
+            compute_store(x, 0u);
         }
-        group(addr);
+    } else {
+        constexpr int LOGT = (TNT == 512) ? 9 : 8;
+        constexpr int LG = LE - K;                                  // log2 groups per thread
+        constexpr int LB = (LG < 4 - K) ? LG : (K >= 4 ? 0 : 4 - K);   // log2 groups per batch
+        // offsets of the basis groups 2^b * TNT
+        uint32_t gb[LG];
+#pragma unroll
+        for (int b = 0; b < LG; b++) {
+            int x = 1 << (LOGT + b);
+#pragma unroll
+            for (int j = 0; j < K; j++) x = ((x >> op.pos[j]) << (op.pos[j] + 1)) | (x & ((1 << op.pos[j]) - 1));
+            gb[b] = uint32_t(sw<T>(x)) << L::LOGE;
+        }
+        for (int bi = 0; bi < (1 << (LG - LB)); bi++) {
+            uint32_t g0 = 0;
+#pragma unroll
+            for (int b = 0; b < LG - LB; b++)
+                if ((bi >> b) & 1) g0 ^= gb[LB + b];
+            uint32_t gofs[1 << LB];
+            Cx<T> x[1 << LB][D];
+#pragma unroll
+            for (int i = 0; i < (1 << LB); i++) {
+                uint32_t o = g0;
+#pragma unroll
+                for (int b = 0; b < LB; b++)
+                    if ((i >> b) & 1) o ^= gb[b];
+                gofs[i] = o;
+#pragma unroll
+                for (int r = 0; r < D; r++) x[i][r] = L::ld(addr0[r] ^ o);
+            }
+#pragma unroll
+            for (int i = 0; i < (1 << LB); i++) compute_store(x[i], gofs[i]);
+        }
     }
 }
 
@@ -485,15 +509,28 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
     }
     for (; i < nrec; i++) {
         if (op.kind == qs::DEVOP_MAT) {
-            const uint32_t cf = cf_at + ((op.coef - cb) << L::LOGE);
-            // operators of up to 4 qubits (wider ones run as strided sweeps,
-            // which keeps the kernel's registers low enough for the occupancy
-            // the tile's LDS allows)
+            uint32_t cf = op.coef - cb;
+            if (op.kx) {
+                // the qubits the operator is diagonal on that lie outside the
+                // tile are fixed for the whole tile: they pick the block of
+                // coefficients (popcount(present) << k entries each)
+                // (constant indices keep the record's fields in registers)
+                uint32_t e = 0;
+#pragma unroll
+                for (int j = 0; j < 5; j++)
+                    if (j < op.kx) e |= uint32_t((base >> op.xq[j]) & 1) << j;
+                cf += (e * uint32_t(__builtin_popcount(op.present))) << op.k;
+            }
+            cf = cf_at + (cf << L::LOGE);
+            // operators addressing up to 4 tile qubits (wider ones run as
+            // strided sweeps, which keeps the kernel's registers low enough
+            // for the occupancy the tile's LDS allows)
             switch (op.k) {
-            case 1: apply_lds<T, 1, TNT>(ta.t, op, cf, addr); break;
-            case 2: apply_lds<T, 2, TNT>(ta.t, op, cf, addr); break;
-            case 3: apply_lds<T, 3, TNT>(ta.t, op, cf, addr); break;
-            default: apply_lds<T, 4, TNT>(ta.t, op, cf, addr); break;
+            case 0: apply_lds<T, 0, LE, TNT>(ta.t, op, cf, addr); break;
+            case 1: apply_lds<T, 1, LE, TNT>(ta.t, op, cf, addr); break;
+            case 2: apply_lds<T, 2, LE, TNT>(ta.t, op, cf, addr); break;
+            case 3: apply_lds<T, 3, LE, TNT>(ta.t, op, cf, addr); break;
+            default: apply_lds<T, 4, LE, TNT>(ta.t, op, cf, addr); break;
             }
         } else {
             // the same on every lane: keeps the loop (and the record

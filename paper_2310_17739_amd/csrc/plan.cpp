@@ -13,6 +13,13 @@
 // Operators commute when they touch disjoint qubits, so a pass may take an
 // operator from further down the list as long as no skipped operator before
 // it shares one of its qubits.
+//
+// A qubit on which an operator is diagonal (no XOR shift of it moves that
+// qubit: Z letters of a Pauli string, the phase of a controlled phase) need
+// not be in the tile.  Every amplitude of a tile has the same value of that
+// qubit, read from the tile's base index, and it selects which block of the
+// operator's coefficients the tile uses.  Only the moved qubits then count
+// against the tile's width.
 #include <algorithm>
 #include <cmath>
 
@@ -21,7 +28,7 @@
 namespace qs {
 
 void plan_passes(int n, const Lowered &L, const std::vector<uint32_t> &meta_bytes,
-                 const PlanConfig &cfg, std::vector<Pass> *passes) {
+                 const std::vector<uint64_t> &need, const PlanConfig &cfg, std::vector<Pass> *passes) {
     passes->clear();
     const std::vector<Op> &ops = L.ops;
     const int N = int(ops.size());
@@ -135,12 +142,12 @@ void plan_passes(int n, const Lowered &L, const std::vector<uint32_t> &meta_byte
             size_t meta = 0;
             int scanned = 0;
             for (int i = nxt[head]; i != head && scanned < cfg.window; i = nxt[i], scanned++) {
-                uint64_t qm = ops[i].mask();
+                const uint64_t qm = ops[i].mask();
                 if ((qm & blocked) || ops[i].k > cfg.max_tile_k ||
                     (!sel.empty() && meta + meta_bytes[i] > cfg.meta_budget)) {
                     blocked |= qm;
-                } else if (__builtin_popcountll(T | qm) <= t) {
-                    T |= qm;
+                } else if (__builtin_popcountll(T | need[i]) <= t) {
+                    T |= need[i];
                     sel.push_back(i);
                     meta += meta_bytes[i];
                 } else {
@@ -180,8 +187,18 @@ uint32_t op_present(const Op &o, bool sparse) {
     return present ? present : 1u;   // the zero operator keeps one (zero) diagonal
 }
 
-void pack_plan(const std::vector<Op> &ops, const std::vector<uint32_t> &present_of,
-               const std::vector<Pass> &passes, PackedPlan *out) {
+uint64_t op_moved_qubits(const Op &o, uint32_t present) {
+    uint32_t bits = 0;
+    for (int m = 1; m < o.dim(); m++)
+        if ((present >> m) & 1) bits |= uint32_t(m);
+    uint64_t r = 0;
+    for (int j = 0; j < o.k; j++)
+        if ((bits >> j) & 1) r |= uint64_t(1) << o.q[j];
+    return r;
+}
+
+int pack_plan(const std::vector<Op> &ops, const std::vector<uint32_t> &present_of,
+              const std::vector<Pass> &passes, PackedPlan *out) {
     out->ops.clear();
     out->pass_begin.clear();
     out->coef_begin.clear();
@@ -212,32 +229,59 @@ void pack_plan(const std::vector<Op> &ops, const std::vector<uint32_t> &present_
             const size_t blk = size_t(d) * d;
             const int nb = 1 << o.np;
             const uint32_t present = present_of[idx];
+            // Local bit order of the record: the positions addressed (every
+            // qubit for a strided sweep; the tile's qubits in a tiled pass),
+            // then the block qubits.  perm[j'] = the operator's bit at new bit j'.
+            int perm[kMaxK], kin = 0, kx = 0;
+            for (int j = 0; j < o.k; j++)
+                if (p.strided || ((p.tile_mask >> o.q[j]) & 1)) perm[kin++] = j;
+            for (int j = 0; j < o.k; j++)
+                if (!(p.strided || ((p.tile_mask >> o.q[j]) & 1))) perm[kin + kx++] = j;
+            auto old_index = [&](int rn) {
+                int ro = 0;
+                for (int j = 0; j < o.k; j++)
+                    if ((rn >> j) & 1) ro |= 1 << perm[j];
+                return ro;
+            };
+            // present shifts in the new order; a shift that moves a block qubit
+            // cannot be applied from outside the tile
+            uint32_t pres = 0;
+            for (int mn = 0; mn < d; mn++) {
+                if (!((present >> old_index(mn)) & 1)) continue;
+                if (mn >> kin) return QSIM_E_ARG;
+                pres |= 1u << mn;
+            }
             DevOp r{};
             r.coef = uint32_t(out->coefs.size());
-            r.present = present;
-            r.k = uint8_t(o.k);
+            r.present = pres;
+            r.k = uint8_t(kin);
+            r.kx = uint8_t(kx);
             r.kind = DEVOP_MAT;
-            for (int j = 0; j < o.k; j++) {
-                int pos = o.q[j];
-                if (!p.strided) {
-                    // rank of qubit q[j] among the tile qubits
-                    if (pos >= p.c) {
-                        int rnk = p.c;
-                        for (int h = 0; h < p.nhi && p.hi[h] < o.q[j]; h++) rnk++;
-                        pos = rnk;
-                    }
+            for (int j = 0; j < kin; j++) {
+                int pos = o.q[perm[j]];
+                if (!p.strided && pos >= p.c) {
+                    // rank of the qubit among the tile qubits
+                    int rnk = p.c;
+                    for (int h = 0; h < p.nhi && p.hi[h] < pos; h++) rnk++;
+                    pos = rnk;
                 }
                 r.pos[j] = uint8_t(pos);
             }
-            // coefficients: for each basis block, for each present shift m (ascending),
-            // the 2^k diagonal entries M[r][r ^ m], r = 0..2^k-1
+            for (int j = 0; j < kx; j++) r.xq[j] = uint8_t(o.q[perm[kin + j]]);
+            // coefficients: for each basis block b, each block e of the block
+            // qubits, each present shift m (ascending), the 2^kin diagonal
+            // entries M[r][r ^ m] with r = r_in + 2^kin e
+            const int din = 1 << kin;
             for (int b = 0; b < nb; b++)
-                for (int m = 0; m < d; m++) {
-                    if (!((present >> m) & 1)) continue;
-                    for (int row = 0; row < d; row++)
-                        out->coefs.push_back(o.m[b * blk + size_t(row) * d + (row ^ m)]);
-                }
-            out->terms += __builtin_popcount(present);
+                for (int e = 0; e < (1 << kx); e++)
+                    for (int mn = 0; mn < din; mn++) {
+                        if (!((pres >> mn) & 1)) continue;
+                        for (int ri = 0; ri < din; ri++) {
+                            const int rn = ri | (e << kin);
+                            out->coefs.push_back(o.m[b * blk + size_t(old_index(rn)) * d + old_index(rn ^ mn)]);
+                        }
+                    }
+            out->terms += __builtin_popcount(pres);
             out->ops.push_back(r);
             out->op_np.push_back(int8_t(o.np));
             for (int j = 0; j < 3; j++) out->op_slots.push_back(o.slot[j]);
@@ -245,6 +289,7 @@ void pack_plan(const std::vector<Op> &ops, const std::vector<uint32_t> &present_
     }
     out->pass_begin.push_back(uint32_t(out->ops.size()));
     out->coef_begin.push_back(uint32_t(out->coefs.size()));
+    return QSIM_OK;
 }
 
 }  // namespace qs

@@ -21,7 +21,7 @@ LIB_PATH = os.environ.get("QSIM_LIB") or os.path.join(_HERE, "libqsim.so")
 C64, C128 = 1, 2
 OK, E_ARG, E_QUBIT, E_NOMEM, E_ZERO_PROB, E_NOT_DEFINITE, E_HIP, E_CAPACITY, E_UNSUPPORTED = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
-F_ONE_OP_PER_PASS, F_NO_SPARSE = 1, 2
+F_ONE_OP_PER_PASS, F_NO_SPARSE, F_FULL_SUPPORT = 1, 2, 4
 
 
 class QsimError(RuntimeError):

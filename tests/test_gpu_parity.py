@@ -286,3 +286,23 @@ def test_program_graph_replays_match_eager(Q, dtype):
         assert np.array_equal(sv.qsim_get_state(), want), rep
     ref, _, _ = oracle.run(n, g)
     check_state(want, ref, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+@pytest.mark.parametrize("p_diag", [0.8, 1.0])
+@pytest.mark.parametrize("n,tile", [(16, 9), (17, None)])
+def test_block_qubits_outside_tile(Q, dtype, p_diag, n, tile):
+    """Qubits an operator is diagonal on may stay outside the tile, where the
+    tile's base index picks the operator's coefficient block.  With p_diag = 1
+    every operator is diagonal on all its qubits (no qubit addressed in the
+    tile).  Both plans match the oracle, and the default one takes fewer
+    passes than keeping every operator qubit in the tile."""
+    g = W.diagonal_rich_circuit(n, 500, seed=n + int(10 * p_diag), p_diag=p_diag)
+    want, _, _ = oracle.run(n, g)
+    passes = {}
+    for flags in (0, Q.F_FULL_SUPPORT):
+        say("block qubits", dtype, p_diag, n, tile, flags)
+        sv = run_gpu(Q, n, g, dtype, tile_qubits=tile, flags=flags)
+        check_state(sv.qsim_get_state(), want, dtype)
+        passes[flags] = sv.qsim_last_stats()["passes"]
+    assert passes[0] < passes[Q.F_FULL_SUPPORT], passes

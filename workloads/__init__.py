@@ -168,6 +168,27 @@ def random_all_kinds(n: int, n_gates: int, seed: int,
     return out
 
 
+def diagonal_rich_circuit(n: int, n_gates: int, seed: int, p_diag: float = 0.8) -> np.ndarray:
+    """Random circuit in which a fraction ``p_diag`` of the gates is diagonal
+    (Z, S, T, Rz, U1, CZ, CU1, CRZ, RZZ) and the rest mixes (H, Rx, Ry, CX,
+    CRY); p_diag = 1 gives a circuit diagonal on every qubit.  Qubits uniform
+    without replacement, angles U[0, 2pi)."""
+    rng = _rng(seed, 91)
+    diag = [KIND_Z, KIND_S, KIND_T, KIND_RZ, KIND_U1, KIND_CZ, KIND_CU1, KIND_CRZ, KIND_RZZ]
+    mix = [KIND_H, KIND_RX, KIND_RY, KIND_CX, KIND_CRY]
+    out = np.zeros(n_gates, dtype=GATE_DTYPE)
+    out["slot"] = -1
+    for i in range(n_gates):
+        pool = diag if rng.random() < p_diag else mix
+        k = pool[rng.integers(len(pool))]
+        a = KIND_QUBITS[k]
+        out[i]["kind"] = k
+        out[i]["nq"] = a
+        out[i]["q"][:a] = rng.choice(n, size=a, replace=False)
+        out[i]["theta"][0] = rng.uniform(0.0, 2.0 * math.pi)
+    return out
+
+
 # ------------------------------------------------------------------ config 2
 def pauli_strings(n: int, count: int, rng: np.random.Generator,
                   wmin: int = 2, wmax: int = 4):
