@@ -245,6 +245,43 @@ __device__ __forceinline__ void apply_chunk_lds(const Cx<T> (&x)[1 << K], Cx<T> 
     }
 }
 
+// y[i][r] = sum over present shifts m of d_m[r] * x[i][r ^ m] for NB groups
+// that share the operator: each coefficient is read from LDS once (a
+// broadcast read) and applied to every group, in ascending m as above.
+template <typename T, int K, int NB>
+__device__ __forceinline__ void apply_groups_lds(const Cx<T> (&x)[NB][1 << K], Cx<T> (&y)[NB][1 << K],
+                                                 uint32_t present, uint32_t cfb) {
+    using L = LdsTile<T>;
+    constexpr int D = 1 << K;
+    uint32_t c = cfb;
+    if (present & 1u) {
+#pragma unroll
+        for (int r = 0; r < D; r++) {
+            const Cx<T> cv = L::ld(c + (uint32_t(r) << L::LOGE));
+#pragma unroll
+            for (int i = 0; i < NB; i++) y[i][r] = cmul(cv, x[i][r]);
+        }
+        c += uint32_t(D) << L::LOGE;
+    } else {
+#pragma unroll
+        for (int i = 0; i < NB; i++)
+#pragma unroll
+            for (int r = 0; r < D; r++) y[i][r] = Cx<T>{T(0), T(0)};
+    }
+#pragma unroll
+    for (int m = 1; m < D; m++) {
+        if (present & (1u << m)) {
+#pragma unroll
+            for (int r = 0; r < D; r++) {
+                const Cx<T> cv = L::ld(c + (uint32_t(r) << L::LOGE));
+#pragma unroll
+                for (int i = 0; i < NB; i++) cmac(y[i][r], cv, x[i][r ^ m]);
+            }
+            c += uint32_t(D) << L::LOGE;
+        }
+    }
+}
+
 // Byte addresses of the members of a thread's first group (g = threadIdx.x)
 // for an operator of at most 4 qubits: they depend on its record only, so they
 // are computed before the barrier that ends the previous operator.  Entries
@@ -333,8 +370,12 @@ __device__ __forceinline__ void apply_lds(int t, const OpRec &op, uint32_t cfb, 
 #pragma unroll
                 for (int r = 0; r < D; r++) x[i][r] = L::ld(addr0[r] ^ o);
             }
+            Cx<T> y[1 << LB][D];
+            apply_groups_lds<T, K, (1 << LB)>(x, y, op.present, cfb);
 #pragma unroll
-            for (int i = 0; i < (1 << LB); i++) compute_store(x[i], gofs[i]);
+            for (int i = 0; i < (1 << LB); i++)
+#pragma unroll
+                for (int r = 0; r < D; r++) L::st(addr0[r] ^ gofs[i], y[i][r]);
         }
     }
 }
