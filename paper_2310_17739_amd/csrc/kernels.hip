@@ -226,10 +226,17 @@ __device__ __forceinline__ void apply_chunk_lds(const Cx<T> (&x)[1 << K], Cx<T> 
     using L = LdsTile<T>;
     constexpr int D = 1 << K;
     uint32_t c = cfb + (uint32_t(R0) << L::LOGE);
+    // A shift's RC coefficients are all read before its first multiply-add
+    // (the scheduling barrier keeps the reads together), so that one LDS
+    // latency covers them.
+    Cx<T> cv[RC];
     // the main diagonal (present in most operators) starts the sums
     if (present & 1u) {
 #pragma unroll
-        for (int r = 0; r < RC; r++) y[r] = cmul(L::ld(c + (uint32_t(r) << L::LOGE)), x[R0 + r]);
+        for (int r = 0; r < RC; r++) cv[r] = L::ld(c + (uint32_t(r) << L::LOGE));
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r = 0; r < RC; r++) y[r] = cmul(cv[r], x[R0 + r]);
         c += uint32_t(D) << L::LOGE;
     } else {
 #pragma unroll
@@ -239,7 +246,10 @@ __device__ __forceinline__ void apply_chunk_lds(const Cx<T> (&x)[1 << K], Cx<T> 
     for (int m = 1; m < D; m++) {
         if (present & (1u << m)) {
 #pragma unroll
-            for (int r = 0; r < RC; r++) cmac(y[r], L::ld(c + (uint32_t(r) << L::LOGE)), x[(R0 + r) ^ m]);
+            for (int r = 0; r < RC; r++) cv[r] = L::ld(c + (uint32_t(r) << L::LOGE));
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int r = 0; r < RC; r++) cmac(y[r], cv[r], x[(R0 + r) ^ m]);
             c += uint32_t(D) << L::LOGE;
         }
     }
@@ -254,13 +264,15 @@ __device__ __forceinline__ void apply_groups_lds(const Cx<T> (&x)[NB][1 << K], C
     using L = LdsTile<T>;
     constexpr int D = 1 << K;
     uint32_t c = cfb;
+    Cx<T> cv[D];
     if (present & 1u) {
 #pragma unroll
-        for (int r = 0; r < D; r++) {
-            const Cx<T> cv = L::ld(c + (uint32_t(r) << L::LOGE));
+        for (int r = 0; r < D; r++) cv[r] = L::ld(c + (uint32_t(r) << L::LOGE));
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int i = 0; i < NB; i++) y[i][r] = cmul(cv, x[i][r]);
-        }
+        for (int r = 0; r < D; r++)
+#pragma unroll
+            for (int i = 0; i < NB; i++) y[i][r] = cmul(cv[r], x[i][r]);
         c += uint32_t(D) << L::LOGE;
     } else {
 #pragma unroll
@@ -272,11 +284,12 @@ __device__ __forceinline__ void apply_groups_lds(const Cx<T> (&x)[NB][1 << K], C
     for (int m = 1; m < D; m++) {
         if (present & (1u << m)) {
 #pragma unroll
-            for (int r = 0; r < D; r++) {
-                const Cx<T> cv = L::ld(c + (uint32_t(r) << L::LOGE));
+            for (int r = 0; r < D; r++) cv[r] = L::ld(c + (uint32_t(r) << L::LOGE));
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int i = 0; i < NB; i++) cmac(y[i][r], cv, x[i][r ^ m]);
-            }
+            for (int r = 0; r < D; r++)
+#pragma unroll
+                for (int i = 0; i < NB; i++) cmac(y[i][r], cv[r], x[i][r ^ m]);
             c += uint32_t(D) << L::LOGE;
         }
     }
