@@ -378,8 +378,9 @@ def main():
                     "trajectories,batched,served,mma,wide (or 'all')")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); "
-              "sharding across GPUs is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no "
+              "multi-GPU path; the states of a batch or a server are independent and would "
+              "shard by whole states", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
