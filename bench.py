@@ -25,6 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# LDS: 128 bytes per clock per CU (32 banks of 4 bytes), 256 CUs at 2.4 GHz
+LDS_PEAK_GBS = 128 * 256 * 2.4
 
 # HBM bytes per launch of the tile kernel at 21 qubits, from two counter runs
 # of this benchmark (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE; KiB per
@@ -113,9 +115,17 @@ def run_trajectories(qsim, W, ntraj=1024, rounds=500):
     info = b.qsim_batch_info()
     b.close()
     p = res["probs"]
+    # The 128 KiB state stays in one workgroup's LDS for the whole program, so
+    # LDS bounds this form: every fused operator reads and writes the state
+    # there once, and each measurement or reset record reads it and rewrites
+    # it (counted as one more read and write).
+    lds_bytes = ntraj * (info["fused_ops"] + 4 * rounds) * 2 * 8 * (1 << 14)
     return {"workload": f"{ntraj} trajectories x {rounds} rounds, 14 qubits, complex64",
             "seconds": dt, "trajectory_rounds_per_s": ntraj * rounds / dt,
             "input_gates_per_s": ntraj * len(g) / dt, "passes": info["passes"],
+            "fused_ops_per_trajectory": info["fused_ops"],
+            "lds": {"bytes": lds_bytes, "achieved_GBps": lds_bytes / dt / 1e9, "peak_GBps": LDS_PEAK_GBS,
+                    "frac": lds_bytes / dt / 1e9 / LDS_PEAK_GBS},
             "failed": int((res["status"] != 0).sum()),
             "mean_p_outcome": float(p.mean()), "norm_max_dev": float(np.abs(res["norms"] - 1).max())}
 
@@ -465,6 +475,12 @@ def main():
                           "achieved_TFLOPs": flops / (float(np.mean(prog_ms)) * 1e-3) / 1e12,
                           "peak_TFLOPs": 78.6,
                           "frac": flops / (float(np.mean(prog_ms)) * 1e-3) / 1e12 / 78.6}
+            # LDS traffic of the same launches: every operator reads and
+            # writes the whole tile once (coefficient reads not counted)
+            lds_bytes = float(st["fused_ops"]) * pass_bytes
+            lds_gbs = lds_bytes / (float(np.mean(prog_ms)) * 1e-3) / 1e9
+            res["lds"] = {"bytes_per_step": lds_bytes, "achieved_GBps": lds_gbs,
+                          "peak_GBps": LDS_PEAK_GBS, "frac": lds_gbs / LDS_PEAK_GBS}
         prog.close()
         sv.close()
         return res
@@ -513,14 +529,14 @@ def main():
         "energy": main_res["energy"],
         "norm": main_res["norm"],
     }
-    for k in ("program_ms_per_step", "avg_launch_us", "per_pass_kernel_us", "alu"):
+    for k in ("program_ms_per_step", "avg_launch_us", "per_pass_kernel_us", "alu", "lds"):
         if k in main_res:
             out[k] = main_res[k]
     if forms:
         out["forms"] = forms
     if other is not None:
         out["other_dtype"] = {k: other[k] for k in ("dtype", "ms_per_step", "gates_per_s", "energy")}
-        for k in ("roofline", "avg_launch_us", "per_pass_kernel_us", "alu"):
+        for k in ("roofline", "avg_launch_us", "per_pass_kernel_us", "alu", "lds"):
             if k in other:
                 out["other_dtype"][k] = other[k]
     print(json.dumps(out), flush=True)
