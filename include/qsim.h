@@ -408,6 +408,19 @@ int qsim_debug_fuse(int n, const qsim_gate *g, size_t ng, const double *mats,
 int qsim_parse_qasm(const char *text, size_t len, qsim_gate *out, size_t cap, size_t *n_out,
                     int32_t *n_qubits, int32_t *n_clbits);
 
+/* Host-only: applies the circuit to psi exactly as the device tables of its
+ * compiled plan describe (the same lowering, fusion, pass plan and packing as
+ * qsim_compile for n and dtype), in FP64 on the host: tiled passes gather each
+ * tile through its position table, apply every operator record with the
+ * coefficient block its block qubits select, and scatter the tile back;
+ * strided passes apply their operator on global positions.  For tests of the
+ * planner and the packer without a GPU.
+ *
+ * psi: 2^n interleaved complex128 values, updated in place (caller-owned).
+ * Errors: as qsim_compile, and QSIM_E_ARG for n > 24 or psi == NULL. */
+int qsim_debug_emulate(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
+                       const double *params, const qsim_fuse_opts *opt, double *psi);
+
 /* Host-only: number of full-state passes the planner makes for the fused
  * circuit (same inputs as qsim_debug_fuse), for n qubits and dtype. */
 int qsim_debug_plan(int n, int dtype, const qsim_gate *g, size_t ng,

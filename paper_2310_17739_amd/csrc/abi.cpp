@@ -941,6 +941,88 @@ int qsim_parse_qasm(const char *text, size_t len, qsim_gate *out, size_t cap, si
     return QSIM_OK;
 }
 
+int qsim_debug_emulate(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
+                       const double *params, const qsim_fuse_opts *opt, double *psi) {
+    if (n < 1 || n > 24 || (dtype != QSIM_C64 && dtype != QSIM_C128) || !psi) return QSIM_E_ARG;
+    Compiled c;
+    int rc;
+    try {
+        rc = compile_circuit(n, dtype, g, ng, mats, params, opt, &c);
+    } catch (const std::bad_alloc &) {
+        return QSIM_E_NOMEM;
+    }
+    if (rc) return rc;
+    const PackedPlan &p = c.plan;
+    cd *st = reinterpret_cast<cd *>(psi);
+    // y[r] = sum over present shifts (ascending) of cf[term * 2^k + r] x[r ^ m]
+    // on the 2^k members of every group of a width-w array addressed by pos[]
+    auto apply = [&](cd *v, int w, const DevOp &o, const cd *cf) {
+        const int k = o.k, d = 1 << k;
+        std::vector<cd> x(d), y(d);
+        for (uint64_t grp = 0; grp < (uint64_t(1) << (w - k)); grp++) {
+            uint64_t b0 = grp;
+            for (int j = 0; j < k; j++)
+                b0 = ((b0 >> o.pos[j]) << (o.pos[j] + 1)) | (b0 & ((uint64_t(1) << o.pos[j]) - 1));
+            auto at = [&](int r) {
+                uint64_t a = b0;
+                for (int j = 0; j < k; j++)
+                    if ((r >> j) & 1) a |= uint64_t(1) << o.pos[j];
+                return a;
+            };
+            for (int r = 0; r < d; r++) x[r] = v[at(r)];
+            for (int r = 0; r < d; r++) {
+                cd acc = 0;
+                int term = 0;
+                for (int m = 0; m < d; m++)
+                    if ((o.present >> m) & 1) acc += cf[size_t(term++) * d + r] * x[r ^ m];
+                y[r] = acc;
+            }
+            for (int r = 0; r < d; r++) v[at(r)] = y[r];
+        }
+    };
+    for (size_t i = 0; i < c.passes.size(); i++) {
+        const PassInfo &pi = c.passes[i];
+        if (pi.kind == Pass::MEASURE) return QSIM_E_ARG;
+        if (pi.strided) {
+            for (uint32_t j = p.pass_begin[i]; j < p.pass_begin[i + 1]; j++) {
+                const DevOp &o = p.ops[j];
+                if (o.kind != DEVOP_MAT || o.kx) return QSIM_E_ARG;
+                apply(st, n, o, p.coefs.data() + o.coef);
+            }
+            continue;
+        }
+        const qk::TileArgs &ta = pi.ta;
+        const int t = ta.t;
+        std::vector<cd> v(size_t(1) << t);
+        for (uint64_t tile = 0; tile < (uint64_t(1) << (n - t)); tile++) {
+            // the tile index deposited into the qubits outside the tile
+            uint64_t base = 0, bits = tile;
+            for (int q = 0; q < n; q++)
+                if ((ta.rest_mask >> q) & 1) {
+                    if (bits & 1) base |= uint64_t(1) << q;
+                    bits >>= 1;
+                }
+            auto addr = [&](uint64_t jpos) {
+                uint64_t a = base;
+                for (int b = 0; b < t; b++)
+                    if ((jpos >> b) & 1) a |= uint64_t(1) << ta.tq[b];
+                return a;
+            };
+            for (uint64_t jpos = 0; jpos < v.size(); jpos++) v[jpos] = st[addr(jpos)];
+            for (uint32_t j = p.pass_begin[i]; j < p.pass_begin[i + 1]; j++) {
+                const DevOp &o = p.ops[j];
+                if (o.kind != DEVOP_MAT) return QSIM_E_ARG;
+                uint32_t e = 0;
+                for (int x = 0; x < o.kx; x++) e |= uint32_t((base >> o.xq[x]) & 1) << x;
+                apply(v.data(), t, o,
+                      p.coefs.data() + o.coef + size_t(e) * (size_t(__builtin_popcount(o.present)) << o.k));
+            }
+            for (uint64_t jpos = 0; jpos < v.size(); jpos++) st[addr(jpos)] = v[jpos];
+        }
+    }
+    return QSIM_OK;
+}
+
 int qsim_debug_plan(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
                     const double *params, const qsim_fuse_opts *opt, qsim_apply_stats *out) {
     if (n < 1 || n > kMaxQubits || (dtype != QSIM_C64 && dtype != QSIM_C128) || !out) return QSIM_E_ARG;

@@ -95,6 +95,7 @@ def _load():
         "qsim_program_stats": ([P, P], I),
         "qsim_program_destroy": ([P], I),
         "qsim_debug_plan": ([I, I, P, SZ, P, P, P, P], I),
+        "qsim_debug_emulate": ([I, I, P, SZ, P, P, P, P], I),
         "qsim_autotune": ([P, P, SZ, P, P, SZ, P, P], I),
         "qsim_sample": ([P, P, SZ, P], I),
         "qsim_batch_create": ([P, I, P, P], I),
@@ -582,6 +583,24 @@ def qsim_parse_qasm(text):
             raise QsimError(rc, "qsim_parse_qasm: " + _lib.qsim_last_error().decode())
         return out[:n_out.value], nq.value, nc.value
     check(rc, "qsim_parse_qasm")
+
+
+def qsim_debug_emulate(n, gates, dtype="complex128", mats=None, params=None, level=None,
+                       max_width=None, tile_qubits=None, flags=0, psi=None) -> np.ndarray:
+    """Host-only: the state after the circuit, applied in FP64 from the packed
+    device tables of the plan compiled for n and dtype (|0...0> if psi is None)."""
+    g = np.ascontiguousarray(gates, dtype=GATE_DTYPE)
+    m = None if mats is None else np.ascontiguousarray(mats, dtype=np.complex128)
+    pr = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+    o = _opts(level, max_width, tile_qubits, flags)
+    if psi is None:
+        out = np.zeros(1 << int(n), dtype=np.complex128)
+        out[0] = 1.0
+    else:
+        out = np.array(psi, dtype=np.complex128, copy=True)
+    check(_lib.qsim_debug_emulate(int(n), QSIM_DTYPES[dtype], _p(g), len(g), _p(m), _p(pr),
+                                  C.byref(o) if o else None, _p(out)), "qsim_debug_emulate")
+    return out
 
 
 def qsim_debug_plan(n, gates, dtype="complex128", mats=None, params=None, level=None,

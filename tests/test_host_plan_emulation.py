@@ -1,0 +1,74 @@
+"""Host-only checks of the pass planner and the packer (no GPU needed).
+
+qsim_debug_emulate applies a circuit in FP64 from the packed device tables
+of its compiled plan, reading the fields the tile kernel reads:
+- the tile position table;
+- the operator records (tile positions, present shifts, block qubits);
+- the coefficient blocks.
+
+The result must equal the oracle's plain gate-by-gate run (fusion is exact
+matrix algebra, Section 3.2). This covers tile passes of every width, the
+qubits an operator leaves outside its tile, resident whole-state passes,
+strided sweeps of wide operators, and one-operator-per-pass plans.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from paper_2310_17739_amd import qsim
+
+
+def check(got, want, rel=1e-12):
+    assert oracle.infidelity(want, got) < 1e-12
+    assert np.max(np.abs(got - want)) < rel * max(1.0, np.max(np.abs(want)))
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+@pytest.mark.parametrize("n,tile", [(8, 5), (12, 8), (15, 9), (16, 12)])
+@pytest.mark.parametrize("gen", ["all_kinds", "pauli", "diagonal"])
+def test_packed_plan_equals_oracle(dtype, n, tile, gen):
+    if gen == "all_kinds":
+        g = W.random_all_kinds(n, 300, seed=n)
+    elif gen == "pauli":
+        g, _, _ = W.pauli_exponential_circuit(n, 80, seed=n)
+    else:
+        g = W.diagonal_rich_circuit(n, 300, seed=n, p_diag=0.8)
+    want, _, _ = oracle.run(n, g)
+    for flags in (0, qsim.F_FULL_SUPPORT):
+        check(qsim.qsim_debug_emulate(n, g, dtype, tile_qubits=tile, flags=flags), want)
+
+
+def test_fully_diagonal_operators_outside_every_tile():
+    """Operators diagonal on all their qubits address no tile position."""
+    n = 14
+    g = W.diagonal_rich_circuit(n, 400, seed=5, p_diag=1.0)
+    psi0 = W.random_state(n, 2)
+    want, _, _ = oracle.run(n, g, psi=psi0)
+    check(qsim.qsim_debug_emulate(n, g, "complex128", tile_qubits=8, psi=psi0), want)
+
+
+def test_dense_matrices_wide_operators_and_single_operator_passes():
+    """Dense matrix records in both qubit orders, 5-qubit fused operators
+    (strided sweeps) and plans with one operator per pass."""
+    n = 11
+    rng = np.random.default_rng(7)
+    recs, mats = [], []
+    for i in range(60):
+        k = int(rng.integers(1, 4))
+        qs = list(rng.choice(n, size=k, replace=False))
+        recs.append((W.KIND_MAT, qs, ()))
+        mats.append(W.random_complex_matrix(1 << k, seed=100 + i).ravel())
+    g = W.gates(recs)
+    o = 0
+    for i in range(len(g)):
+        g[i]["mat_off"] = o
+        o += len(mats[i])
+    allm = np.concatenate(mats)
+    psi0 = W.random_state(n, 3)
+    want, _, _ = oracle.run(n, g, psi=psi0, mats=allm)
+    for kw in ({"tile_qubits": 7}, {"tile_qubits": 7, "max_width": 5},
+               {"flags": qsim.F_ONE_OP_PER_PASS}, {"tile_qubits": 11}):
+        got = qsim.qsim_debug_emulate(n, g, "complex64", mats=allm, psi=psi0, **kw)
+        # random non-unitary factors: compare relative to the result's size
+        check(got, want, rel=1e-10)
