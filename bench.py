@@ -32,21 +32,30 @@ LDS_PEAK_GBS = 128 * 256 * 2.4
 # of this benchmark (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE; KiB per
 # dispatch).  A plain 128 MiB device copy dispatch reads FETCH_SIZE = 65,543 KiB
 # and WRITE_SIZE = 131,072 KiB, so fetches scale by 2.0 and writes by 1.0.
-# The figures hold for the kernel source with the hash below; for any other
-# source the traffic is reported as null.
+# The figures hold for the kernel sources with the hash below (see
+# kernel_source_hash); for any other source the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "kernels_sha256_16": "ba68c14f1d3986ca",
-    "complex128": (16556.6 * 2.0 + 32777.0) * 1024,
-    "complex64": (8326.0 * 2.0 + 16386.1) * 1024,
+    "kernels_sha256_16": "be9a05a55e2bc200",
+    "complex128": (16566.2 * 2.0 + 32776.8) * 1024,
+    "complex64": (8313.8 * 2.0 + 16386.7) * 1024,
 }
 
 
-def measured_traffic(dtype):
+KERNEL_SOURCES = ("kernels.hip", "launch.h", "swizzle.h", "host.h")
+
+
+def kernel_source_hash():
+    """sha256 prefix over the sources the kernels are compiled from."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2310_17739_amd", "csrc", "kernels.hip")
-    with open(src, "rb") as f:
-        h = hashlib.sha256(f.read()).hexdigest()[:16]
-    return MEASURED_TRAFFIC.get(dtype) if h == MEASURED_TRAFFIC["kernels_sha256_16"] else None
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2310_17739_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(dtype):
+    return MEASURED_TRAFFIC.get(dtype) if kernel_source_hash() == MEASURED_TRAFFIC["kernels_sha256_16"] else None
 
 
 def log(*a):
