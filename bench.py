@@ -105,6 +105,25 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
 
 
+def copy_rate_gbs(n_elems, dtype, reps=20):
+    """Rate of a plain device copy of a buffer of n_elems elements (bytes read
+    plus bytes written, per second): the ceiling a pass over a state of the
+    same size can reach."""
+    import torch
+    src = torch.zeros(n_elems, dtype=dtype, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    nbytes = 2 * src.element_size() * n_elems
+    return nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+
+
 def run_trajectories(qsim, W, ntraj=1024, rounds=500):
     """Mid-circuit measurement form: 12 system + 2 ancilla qubits, complex64
     states with FP64 reductions, `rounds` rounds of gates + 2 measurements +
@@ -466,8 +485,10 @@ def main():
             achieved = pass_bytes / (avg_ms * 1e-3) / 1e9
             res["program_ms_per_step"] = float(np.mean(prog_ms))
             res["avg_launch_us"] = avg_ms * 1e3
+            copy_gbs = copy_rate_gbs(1 << n, torch.complex128 if elem == 16 else torch.complex64)
             res["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dtype),
+                               "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                                "kernel": f"k_tile<{'double' if elem == 16 else 'float'}, LE, "
                                          f"{os.environ.get('QSIM_TILE_THREADS') or (256 if elem == 16 else 512)}>",
                                "bytes_per_launch": pass_bytes, "launches_per_step": launches}
