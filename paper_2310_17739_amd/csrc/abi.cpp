@@ -60,6 +60,7 @@ void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc
     // complex64 tiles use 512 threads; complex128 tiles 256, whose groups of
     // 16 outputs then fit the registers without chunking
     pc->threads = env_int("QSIM_TILE_THREADS", dtype == QSIM_C64 ? 512 : 256) == 256 ? 256 : 512;
+    pc->first_in_regs = env_int("QSIM_FIRST_IN_REGS", 1) != 0;
     if (opt) {
         if (opt->level >= 0 && opt->level <= 5) fc->level = opt->level;
         if (opt->max_width > 0) fc->max_width = opt->max_width;
@@ -117,12 +118,26 @@ int validate_plan(int n, int dtype, const Compiled &c) {
                 m |= uint64_t(1) << ta.hi[h];
             }
             if ((m & ta.rest_mask) || ((m | ta.rest_mask) != all) || m != ta.tile_mask) return QSIM_E_ARG;
+            // tile positions: the low qubits first, then every other tile
+            // qubit once
             uint64_t mq = 0;
             for (int j = 0; j < ta.t; j++) {
-                if (j && ta.tq[j] <= ta.tq[j - 1]) return QSIM_E_ARG;
+                if (j < ta.c && ta.tq[j] != j) return QSIM_E_ARG;
+                if (ta.tq[j] >= n || ((mq >> ta.tq[j]) & 1)) return QSIM_E_ARG;
                 mq |= uint64_t(1) << ta.tq[j];
             }
             if (mq != ta.tile_mask) return QSIM_E_ARG;
+            if (ta.first_in_regs) {
+                // the first record runs on a thread's registers: an operator
+                // whose tile positions are the low register-index bits
+                const int logt = ta.threads == 512 ? 9 : 8;
+                if (ta.first_in_regs != 1 || ta.t <= logt || ta.t >= n || p.pass_begin[i] >= p.pass_begin[i + 1])
+                    return QSIM_E_ARG;
+                const DevOp &o = p.ops[p.pass_begin[i]];
+                if (o.kind != DEVOP_MAT || o.k > ta.t - logt || o.k > first_regs_max_k(dtype)) return QSIM_E_ARG;
+                for (int a = 0; a < o.k; a++)
+                    if (o.pos[a] != logt + a) return QSIM_E_ARG;
+            }
             width = ta.t;
         }
         if (p.pass_begin[i] > p.pass_begin[i + 1] || p.pass_begin[i + 1] > p.ops.size()) return QSIM_E_ARG;
@@ -195,6 +210,7 @@ int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const doubl
         need[i] = pc.full_support ? L.ops[i].mask() : op_moved_qubits(L.ops[i], present[i]);
     std::vector<Pass> passes;
     plan_passes(n, L, meta, need, pc, &passes);
+    place_positions(n, L.ops, pc.threads == 512 ? 9 : 8, first_regs_max_k(dtype), pc.first_in_regs, &passes);
     rc = pack_plan(L.ops, present, passes, &out->plan);
     if (rc) return rc;
     // LDS slot offsets of the tile positions (the tile kernel's layout)
@@ -221,12 +237,9 @@ int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const doubl
         pi.ta.rest_mask = all & ~p.tile_mask;
         pi.ta.tile_mask = p.tile_mask;
         pi.ta.threads = pc.threads;
+        pi.ta.first_in_regs = p.first_in_regs ? 1 : 0;
         for (int h = 0; h < p.nhi; h++) pi.ta.hi[h] = uint8_t(p.hi[h]);
-        {
-            int j = 0;
-            for (int q = 0; q < 64 && j < 16; q++)
-                if ((p.tile_mask >> q) & 1) pi.ta.tq[j++] = uint8_t(q);
-        }
+        for (int j = 0; j < 16; j++) pi.ta.tq[j] = p.tq[j];
         out->passes.push_back(pi);
     }
     qsim_apply_stats &s = out->stats;

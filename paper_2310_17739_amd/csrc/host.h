@@ -106,6 +106,8 @@ struct Pass {
     int hi[kMaxQubits] = {0};     // tile qubits >= c, ascending
     std::vector<int> ops;         // operator indices (into the fused list)
     bool strided = false;         // one operator applied by the strided sweep
+    uint8_t tq[16] = {0};         // tiled passes: qubit at tile position j
+    bool first_in_regs = false;   // the first operator runs on the loaded registers
 };
 
 struct PlanConfig {
@@ -117,6 +119,7 @@ struct PlanConfig {
     int threads = 512;            // tile kernel workgroup size (256 or 512)
     bool one_op_per_pass = false;
     bool full_support = false;    // every qubit of an operator in its tile
+    bool first_in_regs = true;    // apply a pass's first operator before the tile reaches LDS
 };
 
 // meta_bytes[i]: LDS bytes operator i needs in a tiled pass (record +
@@ -126,6 +129,20 @@ struct PlanConfig {
 // resident passes (t == n) as records, as passes of their own otherwise.
 void plan_passes(int n, const Lowered &L, const std::vector<uint32_t> &meta_bytes,
                  const std::vector<uint64_t> &need, const PlanConfig &cfg, std::vector<Pass> *passes);
+
+// Tile positions of the tiled passes (t < n).  Positions ascend by qubit
+// (the low c qubits at 0..c-1).  With `first_in_regs`, a tiled pass whose
+// tile spans more than 2^logt elements gets a first operator that the tile
+// kernel applies to a thread's registers as loaded: an operator of the pass
+// that commutes with every operator before it, touches no low qubit and has
+// at most min(t - logt, max_k) qubits in the tile moves to the front, and its
+// tile qubits take positions logt, logt + 1, ... (the bits of a thread's
+// register index).
+void place_positions(int n, const std::vector<Op> &ops, int logt, int max_k, bool first_in_regs,
+                     std::vector<Pass> *passes);
+
+// Widest operator the tile kernel applies to a thread's registers.
+inline int first_regs_max_k(int dtype) { return dtype == QSIM_C64 ? 2 : 4; }
 
 // ---- packing into device tables (plan.cpp)
 // Device operator record (32 bytes, read as eight scalar words): see kernels.hip.

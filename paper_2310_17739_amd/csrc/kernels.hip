@@ -393,6 +393,82 @@ __device__ __forceinline__ void apply_lds(int t, const OpRec &op, uint32_t cfb, 
     }
 }
 
+// The first operator of a pass applied to a thread's registers as loaded:
+// its tile positions are log2(TNT) + j, the bits of the register index i of
+// element tid + i * TNT, so the groups of 2^K members are i = g * 2^K + r.
+// Coefficients are read through uniform addresses; the sums follow the same
+// order as in LDS (main diagonal first, then ascending shifts).
+template <typename T, int K, int LE>
+__device__ __forceinline__ void regs_apply(Cx<T> (&v)[1 << LE], uint32_t present, const Cx<T> *__restrict__ c) {
+    if constexpr (K <= LE) {
+        constexpr int D = 1 << K;
+#pragma unroll
+        for (int g = 0; g < (1 << LE) / D; g++) {
+            Cx<T> x[D], y[D];
+#pragma unroll
+            for (int r = 0; r < D; r++) x[r] = v[g * D + r];
+            uint32_t t0 = 0;
+            if (present & 1u) {
+#pragma unroll
+                for (int r = 0; r < D; r++) y[r] = cmul(c[r], x[r]);
+                t0 = D;
+            } else {
+#pragma unroll
+                for (int r = 0; r < D; r++) y[r] = Cx<T>{T(0), T(0)};
+            }
+#pragma unroll
+            for (int m = 1; m < D; m++) {
+                if (present & (1u << m)) {
+#pragma unroll
+                    for (int r = 0; r < D; r++) cmac(y[r], c[t0 + r], x[r ^ m]);
+                    t0 += D;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < D; r++) v[g * D + r] = y[r];
+        }
+    }
+}
+
+// Widest first operator run on the registers (the host's first_regs_max_k):
+// the host places only operators of at most this many tile qubits there.
+template <typename T>
+constexpr int first_regs_max_k() { return sizeof(T) == 8 ? 4 : 2; }
+
+template <typename T, int LE>
+__device__ __forceinline__ void regs_first(Cx<T> (&v)[1 << LE], const DevOp *__restrict__ rec,
+                                           const Cx<T> *__restrict__ cfs, uint64_t base) {
+    typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+    const U4 a = reinterpret_cast<const U4 *>(rec)[0];
+    const U4 bq = reinterpret_cast<const U4 *>(rec)[1];
+    const uint32_t w[8] = {a.x, a.y, a.z, a.w, bq.x, bq.y, bq.z, bq.w};
+    uint32_t u[8];
+#pragma unroll
+    for (int x = 0; x < 8; x++) u[x] = __builtin_amdgcn_readfirstlane(w[x]);
+    const uint32_t present = u[1];
+    const int k = int(u[2] & 0xff);
+    const int kx = int(u[3] >> 24);
+    const int xq[5] = {int((u[6] >> 16) & 0xff), int(u[6] >> 24), int(u[7] & 0xff), int((u[7] >> 8) & 0xff),
+                       int((u[7] >> 16) & 0xff)};
+    uint32_t cf = u[0];
+    // block qubits outside the tile select the coefficient block (constant
+    // indices keep the fields in registers)
+    uint32_t e = 0;
+#pragma unroll
+    for (int j = 0; j < 5; j++)
+        if (j < kx) e |= uint32_t((base >> xq[j]) & 1) << j;
+    cf += (e * uint32_t(__builtin_popcount(present))) << k;
+    const Cx<T> *c = cfs + cf;
+    constexpr int MK = first_regs_max_k<T>();
+    switch (k) {
+    case 0: regs_apply<T, 0, LE>(v, present, c); break;
+    case 1: regs_apply<T, 1, LE>(v, present, c); break;
+    case 2: regs_apply<T, 2, LE>(v, present, c); break;
+    case 3: if constexpr (MK >= 3) regs_apply<T, 3, LE>(v, present, c); break;
+    default: if constexpr (MK >= 4) regs_apply<T, 4, LE>(v, present, c); break;
+    }
+}
+
 // Scatter the low bits of x into the set bits of m, in ascending order.
 __device__ __forceinline__ uint64_t deposit(uint64_t x, uint64_t m) {
     uint64_t r = 0;
@@ -521,6 +597,12 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
     typedef uint32_t U4 __attribute__((ext_vector_type(4)));
     const U4 *gops = reinterpret_cast<const U4 *>(ops + ob);
     const Cx<T> *gcf = cfs + cb;
+    // The first operator, when placed on the register-index bits, runs on the
+    // loaded tile values before they reach LDS (compiled for 2 to 16 elements
+    // per thread; LE >= 1 means every thread holds E elements).  A tile that
+    // starts as |0...0> leaves it to the operator loop.
+    const bool first_regs =
+        (LE >= 1 && LE <= 4) && ta.first_in_regs && nrec > 0 && !(flags & TF_INIT_ZERO);
     if (flags & TF_INIT_ZERO) {
 #pragma unroll
         for (int i = 0; i < E; i++)
@@ -545,6 +627,9 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
         for (int x = tid; x < 2 * nrec; x += TNT)
             *reinterpret_cast<__attribute__((address_space(3))) U4 *>(uintptr_t(rec_at + 16u * x)) = gops[x];
         for (int x = tid; x < ncf; x += TNT) L::st(cf_at + (uint32_t(x) << L::LOGE), gcf[x]);
+        if constexpr (LE >= 1 && LE <= 4) {
+            if (first_regs) regs_first<T, LE>(v, ops + ob, cfs, base);
+        }
 #pragma unroll
         for (int i = 0; i < E; i++)
             if (active) L::st(stid ^ (uint32_t(sw<T>(i * TNT)) << L::LOGE), v[i]);
@@ -552,13 +637,13 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
     __syncthreads();
 
     int status = 0;
-    int i = 0;
+    int i = first_regs ? 1 : 0;
     // the next operator's record and addresses are prepared before the
     // barrier that ends the current one
     OpRec op{};
     uint32_t addr[16];
-    if (nrec > 0) {
-        op = decode_op(rec_at);
+    if (i < nrec) {
+        op = decode_op(rec_at + uint32_t(i) * uint32_t(sizeof(DevOp)));
         if (op.kind == qs::DEVOP_MAT) prep_addr<T>(op, addr);
     }
     for (; i < nrec; i++) {
@@ -603,17 +688,17 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
         if (ma.fail_at) ma.fail_at[b] = int(ob) + i;
     }
     if (!(flags & TF_NO_STORE)) {
-        Cx<T> v[E];
+        Cx<T> w[E];
 #pragma unroll
         for (int i2 = 0; i2 < E; i2++)
-            if (active) v[i2] = L::ld(stid ^ (uint32_t(sw<T>(i2 * TNT)) << L::LOGE));
+            if (active) w[i2] = L::ld(stid ^ (uint32_t(sw<T>(i2 * TNT)) << L::LOGE));
 #pragma unroll
         for (int i2 = 0; i2 < E; i2++) {
             uint64_t io = 0;
 #pragma unroll
             for (int bt = 0; bt < LE; bt++)
                 if ((i2 >> bt) & 1) io |= ibit[bt];
-            if (active) st_stream(st + (base | toff | io), v[i2]);
+            if (active) st_stream(st + (base | toff | io), w[i2]);
         }
     }
 }

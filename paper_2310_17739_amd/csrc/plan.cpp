@@ -59,6 +59,9 @@ void plan_passes(int n, const Lowered &L, const std::vector<uint32_t> &meta_byte
         p.tile_mask = T;
         for (int q = c; q < n; q++)
             if ((T >> q) & 1) p.hi[p.nhi++] = q;
+        int j = 0;
+        for (int q = 0; q < n && j < 16; q++)
+            if ((T >> q) & 1) p.tq[j++] = uint8_t(q);
         return p;
     };
     auto strided = [&](int i) {
@@ -187,6 +190,54 @@ uint32_t op_present(const Op &o, bool sparse) {
     return present ? present : 1u;   // the zero operator keeps one (zero) diagonal
 }
 
+void place_positions(int n, const std::vector<Op> &ops, int logt, int max_k, bool first_in_regs,
+                     std::vector<Pass> *passes) {
+    const uint64_t all = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
+    for (Pass &p : *passes) {
+        if (!first_in_regs || p.kind != Pass::TILE || p.strided || p.tile_mask == all || p.t <= logt ||
+            p.ops.empty())
+            continue;
+        const uint64_t low = (uint64_t(1) << p.c) - 1;
+        const int le = std::min(p.t - logt, max_k);
+        uint64_t before = 0;
+        int pick = -1;
+        for (size_t x = 0; x < p.ops.size(); x++) {
+            const Op &o = ops[p.ops[x]];
+            const uint64_t in = o.mask() & p.tile_mask;
+            if (!(in & low) && !(o.mask() & before) && __builtin_popcountll(in) <= le) {
+                pick = int(x);
+                break;
+            }
+            before |= o.mask();
+        }
+        if (pick < 0) continue;
+        // the operator moves to the front (it commutes with those it passes)
+        const int idx = p.ops[size_t(pick)];
+        p.ops.erase(p.ops.begin() + pick);
+        p.ops.insert(p.ops.begin(), idx);
+        p.seq = p.ops;
+        const uint64_t in = ops[idx].mask() & p.tile_mask;
+        const int kin = __builtin_popcountll(in);
+        // positions 0..c-1: low qubits; logt..logt+kin-1: the operator's tile
+        // qubits; the rest of the tile qubits fill the other positions in
+        // ascending order
+        uint8_t tq[16];
+        int fill[16], nf = 0;
+        for (int q = 0; q < n; q++)
+            if (((p.tile_mask >> q) & 1) && !((low >> q) & 1) && !((in >> q) & 1)) fill[nf++] = q;
+        int f = 0, r = 0;
+        for (int pos = 0; pos < p.t; pos++) {
+            if (pos < p.c) tq[pos] = uint8_t(pos);
+            else if (pos >= logt && pos < logt + kin) {
+                while (!((in >> r) & 1)) r++;
+                tq[pos] = uint8_t(r++);
+            } else tq[pos] = uint8_t(fill[f++]);
+        }
+        for (int pos = 0; pos < p.t; pos++) p.tq[pos] = tq[pos];
+        p.first_in_regs = true;
+    }
+}
+
 uint64_t op_moved_qubits(const Op &o, uint32_t present) {
     uint32_t bits = 0;
     for (int m = 1; m < o.dim(); m++)
@@ -230,13 +281,24 @@ int pack_plan(const std::vector<Op> &ops, const std::vector<uint32_t> &present_o
             const int nb = 1 << o.np;
             const uint32_t present = present_of[idx];
             // Local bit order of the record: the positions addressed (every
-            // qubit for a strided sweep; the tile's qubits in a tiled pass),
-            // then the block qubits.  perm[j'] = the operator's bit at new bit j'.
+            // qubit for a strided sweep; the tile's qubits in a tiled pass,
+            // by ascending tile position), then the block qubits.
+            // perm[j'] = the operator's bit at new bit j'.
+            int tpos[kMaxK];
+            for (int j = 0; j < o.k; j++) {
+                tpos[j] = -1;
+                if (p.strided) tpos[j] = o.q[j];
+                else
+                    for (int x = 0; x < p.t && x < 16; x++)
+                        if (p.tq[x] == o.q[j]) tpos[j] = x;
+            }
             int perm[kMaxK], kin = 0, kx = 0;
             for (int j = 0; j < o.k; j++)
-                if (p.strided || ((p.tile_mask >> o.q[j]) & 1)) perm[kin++] = j;
+                if (tpos[j] >= 0) perm[kin++] = j;
+            for (int a = 1; a < kin; a++)
+                for (int b = a; b > 0 && tpos[perm[b]] < tpos[perm[b - 1]]; b--) std::swap(perm[b], perm[b - 1]);
             for (int j = 0; j < o.k; j++)
-                if (!(p.strided || ((p.tile_mask >> o.q[j]) & 1))) perm[kin + kx++] = j;
+                if (tpos[j] < 0) perm[kin + kx++] = j;
             auto old_index = [&](int rn) {
                 int ro = 0;
                 for (int j = 0; j < o.k; j++)
@@ -257,16 +319,7 @@ int pack_plan(const std::vector<Op> &ops, const std::vector<uint32_t> &present_o
             r.k = uint8_t(kin);
             r.kx = uint8_t(kx);
             r.kind = DEVOP_MAT;
-            for (int j = 0; j < kin; j++) {
-                int pos = o.q[perm[j]];
-                if (!p.strided && pos >= p.c) {
-                    // rank of the qubit among the tile qubits
-                    int rnk = p.c;
-                    for (int h = 0; h < p.nhi && p.hi[h] < pos; h++) rnk++;
-                    pos = rnk;
-                }
-                r.pos[j] = uint8_t(pos);
-            }
+            for (int j = 0; j < kin; j++) r.pos[j] = uint8_t(tpos[perm[j]]);
             for (int j = 0; j < kx; j++) r.xq[j] = uint8_t(o.q[perm[kin + j]]);
             // coefficients: for each basis block b, each block e of the block
             // qubits, each present shift m (ascending), the 2^kin diagonal
