@@ -30,14 +30,14 @@ LDS_PEAK_GBS = 128 * 256 * 2.4
 
 # HBM bytes per launch of the tile kernel at 21 qubits, from two counter runs
 # of this benchmark (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE; KiB per
-# dispatch).  A plain 128 MiB device copy dispatch reads FETCH_SIZE = 65,543 KiB
-# and WRITE_SIZE = 131,072 KiB, so fetches scale by 2.0 and writes by 1.0.
+# dispatch).  A plain 256 MiB device copy dispatch reads FETCH_SIZE = 131,085 KiB
+# and WRITE_SIZE = 262,144 KiB, so fetches scale by 2.0 and writes by 1.0.
 # The figures hold for the kernel sources with the hash below (see
 # kernel_source_hash); for any other source the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "kernels_sha256_16": "be9a05a55e2bc200",
-    "complex128": (16566.2 * 2.0 + 32776.8) * 1024,
-    "complex64": (8313.8 * 2.0 + 16386.7) * 1024,
+    "kernels_sha256_16": "39e1194496ee40d5",
+    "complex128": (16625.6 * 2.0 + 32777.9) * 1024,
+    "complex64": (8332.3 * 2.0 + 16386.2) * 1024,
 }
 
 
