@@ -127,16 +127,24 @@ int validate_plan(int n, int dtype, const Compiled &c) {
                 mq |= uint64_t(1) << ta.tq[j];
             }
             if (mq != ta.tile_mask) return QSIM_E_ARG;
-            if (ta.first_in_regs) {
-                // the first record runs on a thread's registers: an operator
-                // whose tile positions are the low register-index bits
+            if (ta.regs) {
+                // operators run on a thread's registers: their tile positions
+                // are consecutive register-index bits (log2(threads) + off + j)
                 const int logt = ta.threads == 512 ? 9 : 8;
-                if (ta.first_in_regs != 1 || ta.t <= logt || ta.t >= n || p.pass_begin[i] >= p.pass_begin[i + 1])
+                const uint32_t rb = p.pass_begin[i], re = p.pass_begin[i + 1];
+                const int first = ta.regs & 1, last = (ta.regs >> 1) & 1, off = (ta.regs >> 2) & 7;
+                if ((ta.regs >> 5) || ta.t <= logt || ta.t >= n || re - rb < uint32_t(first + last)) return QSIM_E_ARG;
+                const int le = std::min(ta.t - logt, 4);
+                auto check_regs = [&](const DevOp &o, int at) {
+                    if (o.kind != DEVOP_MAT || o.k > first_regs_max_k(dtype) || at + o.k > le) return false;
+                    for (int a2 = 0; a2 < o.k; a2++)
+                        if (o.pos[a2] != logt + at + a2) return false;
+                    return true;
+                };
+                if (first && !check_regs(p.ops[rb], 0)) return QSIM_E_ARG;
+                if (last && (!check_regs(p.ops[re - 1], off) || off != (first ? int(p.ops[rb].k) : 0)))
                     return QSIM_E_ARG;
-                const DevOp &o = p.ops[p.pass_begin[i]];
-                if (o.kind != DEVOP_MAT || o.k > ta.t - logt || o.k > first_regs_max_k(dtype)) return QSIM_E_ARG;
-                for (int a = 0; a < o.k; a++)
-                    if (o.pos[a] != logt + a) return QSIM_E_ARG;
+                if (!last && off) return QSIM_E_ARG;
             }
             width = ta.t;
         }
@@ -237,7 +245,7 @@ int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const doubl
         pi.ta.rest_mask = all & ~p.tile_mask;
         pi.ta.tile_mask = p.tile_mask;
         pi.ta.threads = pc.threads;
-        pi.ta.first_in_regs = p.first_in_regs ? 1 : 0;
+        pi.ta.regs = (p.first_in_regs ? 1 : 0) | (p.last_in_regs ? 2 : 0) | (p.last_off << 2);
         for (int h = 0; h < p.nhi; h++) pi.ta.hi[h] = uint8_t(p.hi[h]);
         for (int j = 0; j < 16; j++) pi.ta.tq[j] = p.tq[j];
         out->passes.push_back(pi);

@@ -108,6 +108,8 @@ struct Pass {
     bool strided = false;         // one operator applied by the strided sweep
     uint8_t tq[16] = {0};         // tiled passes: qubit at tile position j
     bool first_in_regs = false;   // the first operator runs on the loaded registers
+    bool last_in_regs = false;    // the last operator runs on the registers stored
+    int last_off = 0;             // its first register-index bit
 };
 
 struct PlanConfig {
@@ -137,7 +139,10 @@ void plan_passes(int n, const Lowered &L, const std::vector<uint32_t> &meta_byte
 // that commutes with every operator before it, touches no low qubit and has
 // at most min(t - logt, max_k) qubits in the tile moves to the front, and its
 // tile qubits take positions logt, logt + 1, ... (the bits of a thread's
-// register index).
+// register index).  Likewise an operator that commutes with every operator
+// after it moves to the end, its tile qubits (disjoint from the first one's)
+// on the next register-index bits: the kernel applies it to the tile as it
+// leaves LDS.
 void place_positions(int n, const std::vector<Op> &ops, int logt, int max_k, bool first_in_regs,
                      std::vector<Pass> *passes);
 

@@ -393,51 +393,72 @@ __device__ __forceinline__ void apply_lds(int t, const OpRec &op, uint32_t cfb, 
     }
 }
 
-// The first operator of a pass applied to a thread's registers as loaded:
-// its tile positions are log2(TNT) + j, the bits of the register index i of
-// element tid + i * TNT, so the groups of 2^K members are i = g * 2^K + r.
-// Coefficients are read through uniform addresses; the sums follow the same
-// order as in LDS (main diagonal first, then ascending shifts).
-template <typename T, int K, int LE>
+// An operator applied to a thread's registers: element tid + i * TNT sits at
+// tile position log2(TNT) + b for bit b of the register index i, so an
+// operator whose tile positions are log2(TNT) + OFF + j has the groups
+// i = hi * 2^(OFF+K) + r * 2^OFF + lo (members r).  The first operator of a
+// pass runs so on the tile as loaded, the last one on the tile as it leaves
+// LDS for the store.  Coefficients are read through uniform addresses; the
+// sums follow the same order as in LDS (main diagonal first, then ascending
+// shifts).
+template <typename T, int K, int OFF, int LE>
 __device__ __forceinline__ void regs_apply(Cx<T> (&v)[1 << LE], uint32_t present, const Cx<T> *__restrict__ c) {
-    if constexpr (K <= LE) {
+    if constexpr (K + OFF <= LE) {
         constexpr int D = 1 << K;
 #pragma unroll
-        for (int g = 0; g < (1 << LE) / D; g++) {
-            Cx<T> x[D], y[D];
+        for (int hi = 0; hi < (1 << (LE - OFF - K)); hi++) {
 #pragma unroll
-            for (int r = 0; r < D; r++) x[r] = v[g * D + r];
-            uint32_t t0 = 0;
-            if (present & 1u) {
+            for (int lo = 0; lo < (1 << OFF); lo++) {
+                Cx<T> x[D], y[D];
 #pragma unroll
-                for (int r = 0; r < D; r++) y[r] = cmul(c[r], x[r]);
-                t0 = D;
-            } else {
+                for (int r = 0; r < D; r++) x[r] = v[(hi << (OFF + K)) | (r << OFF) | lo];
+                uint32_t t0 = 0;
+                if (present & 1u) {
 #pragma unroll
-                for (int r = 0; r < D; r++) y[r] = Cx<T>{T(0), T(0)};
-            }
+                    for (int r = 0; r < D; r++) y[r] = cmul(c[r], x[r]);
+                    t0 = D;
+                } else {
 #pragma unroll
-            for (int m = 1; m < D; m++) {
-                if (present & (1u << m)) {
-#pragma unroll
-                    for (int r = 0; r < D; r++) cmac(y[r], c[t0 + r], x[r ^ m]);
-                    t0 += D;
+                    for (int r = 0; r < D; r++) y[r] = Cx<T>{T(0), T(0)};
                 }
-            }
 #pragma unroll
-            for (int r = 0; r < D; r++) v[g * D + r] = y[r];
+                for (int m = 1; m < D; m++) {
+                    if (present & (1u << m)) {
+#pragma unroll
+                        for (int r = 0; r < D; r++) cmac(y[r], c[t0 + r], x[r ^ m]);
+                        t0 += D;
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < D; r++) v[(hi << (OFF + K)) | (r << OFF) | lo] = y[r];
+            }
         }
     }
 }
 
-// Widest first operator run on the registers (the host's first_regs_max_k):
-// the host places only operators of at most this many tile qubits there.
+// Widest operator run on the registers (the host's first_regs_max_k): the
+// host places only operators of at most this many tile qubits there.
 template <typename T>
 constexpr int first_regs_max_k() { return sizeof(T) == 8 ? 4 : 2; }
 
+template <typename T, int OFF, int LE>
+__device__ __forceinline__ void regs_apply_k(Cx<T> (&v)[1 << LE], int k, uint32_t present,
+                                             const Cx<T> *__restrict__ c) {
+    constexpr int MK = first_regs_max_k<T>();
+    switch (k) {
+    case 0: regs_apply<T, 0, OFF, LE>(v, present, c); break;
+    case 1: regs_apply<T, 1, OFF, LE>(v, present, c); break;
+    case 2: regs_apply<T, 2, OFF, LE>(v, present, c); break;
+    case 3: if constexpr (MK >= 3) regs_apply<T, 3, OFF, LE>(v, present, c); break;
+    default: if constexpr (MK >= 4) regs_apply<T, 4, OFF, LE>(v, present, c); break;
+    }
+}
+
+// The record at `rec` (global memory) applied to the registers, its tile
+// positions starting at register-index bit `off`.
 template <typename T, int LE>
-__device__ __forceinline__ void regs_first(Cx<T> (&v)[1 << LE], const DevOp *__restrict__ rec,
-                                           const Cx<T> *__restrict__ cfs, uint64_t base) {
+__device__ __forceinline__ void regs_record(Cx<T> (&v)[1 << LE], const DevOp *__restrict__ rec,
+                                            const Cx<T> *__restrict__ cfs, uint64_t base, int off) {
     typedef uint32_t U4 __attribute__((ext_vector_type(4)));
     const U4 a = reinterpret_cast<const U4 *>(rec)[0];
     const U4 bq = reinterpret_cast<const U4 *>(rec)[1];
@@ -459,13 +480,11 @@ __device__ __forceinline__ void regs_first(Cx<T> (&v)[1 << LE], const DevOp *__r
         if (j < kx) e |= uint32_t((base >> xq[j]) & 1) << j;
     cf += (e * uint32_t(__builtin_popcount(present))) << k;
     const Cx<T> *c = cfs + cf;
-    constexpr int MK = first_regs_max_k<T>();
-    switch (k) {
-    case 0: regs_apply<T, 0, LE>(v, present, c); break;
-    case 1: regs_apply<T, 1, LE>(v, present, c); break;
-    case 2: regs_apply<T, 2, LE>(v, present, c); break;
-    case 3: if constexpr (MK >= 3) regs_apply<T, 3, LE>(v, present, c); break;
-    default: if constexpr (MK >= 4) regs_apply<T, 4, LE>(v, present, c); break;
+    switch (off) {
+    case 0: regs_apply_k<T, 0, LE>(v, k, present, c); break;
+    case 1: regs_apply_k<T, 1, LE>(v, k, present, c); break;
+    case 2: regs_apply_k<T, 2, LE>(v, k, present, c); break;
+    default: regs_apply_k<T, 3, LE>(v, k, present, c); break;
     }
 }
 
@@ -602,7 +621,11 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
     // per thread; LE >= 1 means every thread holds E elements).  A tile that
     // starts as |0...0> leaves it to the operator loop.
     const bool first_regs =
-        (LE >= 1 && LE <= 4) && ta.first_in_regs && nrec > 0 && !(flags & TF_INIT_ZERO);
+        (LE >= 1 && LE <= 4) && (ta.regs & 1) && nrec > 0 && !(flags & TF_INIT_ZERO);
+    // likewise the last operator, on the tile as it leaves LDS for the store
+    const bool last_regs = (LE >= 1 && LE <= 4) && (ta.regs & 2) && nrec > (first_regs ? 1 : 0) &&
+                           !(flags & TF_NO_STORE);
+    const int iend = last_regs ? nrec - 1 : nrec;
     if (flags & TF_INIT_ZERO) {
 #pragma unroll
         for (int i = 0; i < E; i++)
@@ -628,7 +651,7 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
             *reinterpret_cast<__attribute__((address_space(3))) U4 *>(uintptr_t(rec_at + 16u * x)) = gops[x];
         for (int x = tid; x < ncf; x += TNT) L::st(cf_at + (uint32_t(x) << L::LOGE), gcf[x]);
         if constexpr (LE >= 1 && LE <= 4) {
-            if (first_regs) regs_first<T, LE>(v, ops + ob, cfs, base);
+            if (first_regs) regs_record<T, LE>(v, ops + ob, cfs, base, 0);
         }
 #pragma unroll
         for (int i = 0; i < E; i++)
@@ -642,11 +665,11 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
     // barrier that ends the current one
     OpRec op{};
     uint32_t addr[16];
-    if (i < nrec) {
+    if (i < iend) {
         op = decode_op(rec_at + uint32_t(i) * uint32_t(sizeof(DevOp)));
         if (op.kind == qs::DEVOP_MAT) prep_addr<T>(op, addr);
     }
-    for (; i < nrec; i++) {
+    for (; i < iend; i++) {
         if (op.kind == qs::DEVOP_MAT) {
             uint32_t cf = op.coef - cb;
             if (op.kx) {
@@ -676,7 +699,7 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
             // addresses) uniform
             status = __builtin_amdgcn_readfirstlane(lds_measure<T, TNT>(ta.t, op, ma, b));
         }
-        if (i + 1 < nrec) {
+        if (i + 1 < iend) {
             op = decode_op(rec_at + uint32_t(i + 1) * uint32_t(sizeof(DevOp)));
             if (op.kind == qs::DEVOP_MAT) prep_addr<T>(op, addr);
         }
@@ -692,6 +715,9 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
 #pragma unroll
         for (int i2 = 0; i2 < E; i2++)
             if (active) w[i2] = L::ld(stid ^ (uint32_t(sw<T>(i2 * TNT)) << L::LOGE));
+        if constexpr (LE >= 1 && LE <= 4) {
+            if (last_regs && !status) regs_record<T, LE>(w, ops + ob + (nrec - 1), cfs, base, (ta.regs >> 2) & 7);
+        }
 #pragma unroll
         for (int i2 = 0; i2 < E; i2++) {
             uint64_t io = 0;

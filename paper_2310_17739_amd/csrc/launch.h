@@ -16,16 +16,17 @@ int note_hip(hipError_t e, const char *where);
 // Tile of a pass: the qubits outside the tile enumerate the tiles
 // (blockIdx.x); tile position j holds qubit tq[j].  The low c qubits sit at
 // positions 0..c-1 (contiguous chunks in memory); hi[] lists the other tile
-// qubits in ascending order.  Positions ascend by qubit, except that with
-// first_in_regs the first operator's qubits sit at positions log2(threads)
-// + j (a thread's register index bits): it is applied to the tile as loaded,
-// before the tile reaches LDS.
+// qubits in ascending order.  Positions ascend by qubit, except that an
+// operator run on a thread's registers (`regs`) has its qubits at positions
+// log2(threads) + off + j, the bits of the register index: the first one is
+// applied to the tile as loaded, the last one as the tile leaves LDS.
 struct TileArgs {
     uint64_t rest_mask;   // qubits not in the tile
     uint64_t tile_mask;   // qubits in the tile (j bit b <-> b-th lowest of them)
     int32_t n, t, c, nhi;
     int32_t threads;      // workgroup size of the tile kernel: 256 or 512
-    int32_t first_in_regs;  // 1: the first record is applied to the loaded registers
+    int32_t regs;         // bit 0: the first record runs on the loaded registers; bit 1: the
+                          // last one on the registers stored; bits 2-4: its register-bit offset
     uint8_t tq[16];       // qubit at tile position j
     uint8_t hi[48];
 };

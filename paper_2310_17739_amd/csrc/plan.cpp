@@ -198,43 +198,74 @@ void place_positions(int n, const std::vector<Op> &ops, int logt, int max_k, boo
             p.ops.empty())
             continue;
         const uint64_t low = (uint64_t(1) << p.c) - 1;
-        const int le = std::min(p.t - logt, max_k);
+        const int le = std::min(p.t - logt, 4);
+        auto tile_qubits = [&](int idx) { return ops[idx].mask() & p.tile_mask; };
+        auto fits = [&](int idx, int off) {
+            const uint64_t in = tile_qubits(idx);
+            return !(in & low) && __builtin_popcountll(in) <= max_k && off + __builtin_popcountll(in) <= le;
+        };
+        // the first operator: one that commutes with every operator before it
         uint64_t before = 0;
         int pick = -1;
         for (size_t x = 0; x < p.ops.size(); x++) {
             const Op &o = ops[p.ops[x]];
-            const uint64_t in = o.mask() & p.tile_mask;
-            if (!(in & low) && !(o.mask() & before) && __builtin_popcountll(in) <= le) {
+            if (!(o.mask() & before) && fits(p.ops[x], 0)) {
                 pick = int(x);
                 break;
             }
             before |= o.mask();
         }
-        if (pick < 0) continue;
-        // the operator moves to the front (it commutes with those it passes)
-        const int idx = p.ops[size_t(pick)];
-        p.ops.erase(p.ops.begin() + pick);
-        p.ops.insert(p.ops.begin(), idx);
+        uint64_t first_in = 0;
+        int k1 = 0;
+        if (pick >= 0) {
+            const int idx = p.ops[size_t(pick)];
+            p.ops.erase(p.ops.begin() + pick);
+            p.ops.insert(p.ops.begin(), idx);
+            first_in = tile_qubits(idx);
+            k1 = __builtin_popcountll(first_in);
+            p.first_in_regs = true;
+        }
+        // the last operator: one that commutes with every operator after it,
+        // its tile qubits disjoint from the first one's
+        uint64_t after = 0;
+        int lpick = -1;
+        for (int x = int(p.ops.size()) - 1; x >= (p.first_in_regs ? 1 : 0); x--) {
+            const Op &o = ops[p.ops[size_t(x)]];
+            if (!(o.mask() & after) && !(tile_qubits(p.ops[size_t(x)]) & first_in) && fits(p.ops[size_t(x)], k1)) {
+                lpick = x;
+                break;
+            }
+            after |= o.mask();
+        }
+        uint64_t last_in = 0;
+        if (lpick >= 0) {
+            const int idx = p.ops[size_t(lpick)];
+            p.ops.erase(p.ops.begin() + lpick);
+            p.ops.push_back(idx);
+            last_in = tile_qubits(idx);
+            p.last_in_regs = true;
+            p.last_off = k1;
+        }
+        if (!p.first_in_regs && !p.last_in_regs) continue;
         p.seq = p.ops;
-        const uint64_t in = ops[idx].mask() & p.tile_mask;
-        const int kin = __builtin_popcountll(in);
-        // positions 0..c-1: low qubits; logt..logt+kin-1: the operator's tile
-        // qubits; the rest of the tile qubits fill the other positions in
-        // ascending order
-        uint8_t tq[16];
+        // positions 0..c-1: low qubits; logt..: the first operator's tile
+        // qubits, then the last one's; the other tile qubits fill the
+        // remaining positions in ascending order
+        const int k2 = __builtin_popcountll(last_in);
         int fill[16], nf = 0;
         for (int q = 0; q < n; q++)
-            if (((p.tile_mask >> q) & 1) && !((low >> q) & 1) && !((in >> q) & 1)) fill[nf++] = q;
-        int f = 0, r = 0;
+            if (((p.tile_mask >> q) & 1) && !((low | first_in | last_in) >> q & 1)) fill[nf++] = q;
+        int f = 0, r1 = 0, r2 = 0;
         for (int pos = 0; pos < p.t; pos++) {
-            if (pos < p.c) tq[pos] = uint8_t(pos);
-            else if (pos >= logt && pos < logt + kin) {
-                while (!((in >> r) & 1)) r++;
-                tq[pos] = uint8_t(r++);
-            } else tq[pos] = uint8_t(fill[f++]);
+            if (pos < p.c) p.tq[pos] = uint8_t(pos);
+            else if (pos >= logt && pos < logt + k1) {
+                while (!((first_in >> r1) & 1)) r1++;
+                p.tq[pos] = uint8_t(r1++);
+            } else if (pos >= logt + k1 && pos < logt + k1 + k2) {
+                while (!((last_in >> r2) & 1)) r2++;
+                p.tq[pos] = uint8_t(r2++);
+            } else p.tq[pos] = uint8_t(fill[f++]);
         }
-        for (int pos = 0; pos < p.t; pos++) p.tq[pos] = tq[pos];
-        p.first_in_regs = true;
     }
 }
 
