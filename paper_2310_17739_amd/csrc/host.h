@@ -146,8 +146,9 @@ void plan_passes(int n, const Lowered &L, const std::vector<uint32_t> &meta_byte
 void place_positions(int n, const std::vector<Op> &ops, int logt, int max_k, bool first_in_regs,
                      std::vector<Pass> *passes);
 
-// Widest operator the tile kernel applies to a thread's registers.
-inline int first_regs_max_k(int dtype) { return dtype == QSIM_C64 ? 2 : 4; }
+// Widest operator the tile kernel applies to a thread's registers (also
+// bounded by the register-index bits of the tile, t - log2(threads)).
+inline int first_regs_max_k(int) { return 4; }
 
 // ---- packing into device tables (plan.cpp)
 // Device operator record (32 bytes, read as eight scalar words): see kernels.hip.

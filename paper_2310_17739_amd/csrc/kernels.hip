@@ -439,7 +439,7 @@ __device__ __forceinline__ void regs_apply(Cx<T> (&v)[1 << LE], uint32_t present
 // Widest operator run on the registers (the host's first_regs_max_k): the
 // host places only operators of at most this many tile qubits there.
 template <typename T>
-constexpr int first_regs_max_k() { return sizeof(T) == 8 ? 4 : 2; }
+constexpr int first_regs_max_k() { return 4; }
 
 template <typename T, int OFF, int LE>
 __device__ __forceinline__ void regs_apply_k(Cx<T> (&v)[1 << LE], int k, uint32_t present,
