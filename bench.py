@@ -35,9 +35,9 @@ LDS_PEAK_GBS = 128 * 256 * 2.4
 # The figures hold for the kernel sources with the hash below (see
 # kernel_source_hash); for any other source the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "kernels_sha256_16": "7c47baff072e4ba3",
-    "complex128": (16660.1 * 2.0 + 32776.2) * 1024,
-    "complex64": (8374.2 * 2.0 + 16385.8) * 1024,
+    "kernels_sha256_16": "8d480b11cb024c7b",
+    "complex128": (16657.1 * 2.0 + 32780.3) * 1024,
+    "complex64": (8378.7 * 2.0 + 16386.2) * 1024,
 }
 
 
