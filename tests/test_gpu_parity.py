@@ -306,3 +306,23 @@ def test_block_qubits_outside_tile(Q, dtype, p_diag, n, tile):
         check_state(sv.qsim_get_state(), want, dtype)
         passes[flags] = sv.qsim_last_stats()["passes"]
     assert passes[0] < passes[Q.F_FULL_SUPPORT], passes
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+def test_register_operators_on_and_off(Q, dtype, monkeypatch):
+    """The first and last operators of a tiled pass may run on a thread's
+    registers (the tile as loaded, the tile as stored); with the planner's
+    placement switched off every operator runs in LDS.  Both plans match the
+    oracle, on a circuit of mixed kinds, at several tile sizes."""
+    n = 17
+    g = W.random_all_kinds(n, 400, seed=23)
+    psi0 = W.random_state(n, 4)
+    want, _, _ = oracle.run(n, g, psi=psi0)
+    for flag in ("1", "0"):
+        monkeypatch.setenv("QSIM_FIRST_IN_REGS", flag)
+        for tile in (10, 12, 13):
+            say("register operators", dtype, flag, tile)
+            sv = Q.StateVector(n, dtype)
+            sv.qsim_set_state(psi0)
+            sv.qsim_apply(g, tile_qubits=tile)
+            check_state(sv.qsim_get_state(), want, dtype)
