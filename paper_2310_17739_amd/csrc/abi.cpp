@@ -276,8 +276,8 @@ int hip_rc(hipError_t e) { return qk::note_hip(e, "runtime call"); }
 int grow(void **ptr, size_t *cap, size_t need, hipStream_t st) {
     if (need <= *cap) return QSIM_OK;
     if (*ptr) {
-        hipStreamSynchronize(st);
-        hipFree(*ptr);
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(*ptr);
         *ptr = nullptr;
         *cap = 0;
     }
@@ -291,7 +291,7 @@ int grow(void **ptr, size_t *cap, size_t need, hipStream_t st) {
 
 int grow_host(void **ptr, size_t *cap, size_t need) {
     if (need <= *cap) return QSIM_OK;
-    if (*ptr) hipHostFree(*ptr);
+    if (*ptr) (void)hipHostFree(*ptr);
     *ptr = nullptr;
     *cap = 0;
     size_t sz = std::max(need, size_t(4096));
@@ -313,7 +313,7 @@ int upload_plan(DeviceTables *dt, int dtype, const PackedPlan &plan, hipStream_t
     const size_t coef_bytes = plan.coefs.size() * elem_bytes(dtype);
     const size_t ops_pad = (ops_bytes + 255) & ~size_t(255);
     if (dt->stage_ev_valid) {
-        hipEventSynchronize(dt->stage_ev);   // previous upload has left the staging buffer
+        (void)hipEventSynchronize(dt->stage_ev);   // previous upload has left the staging buffer
         dt->stage_ev_valid = false;
     }
     int rc = grow_host(&dt->h_stage, &dt->cap_stage, ops_pad + coef_bytes + 256);
@@ -347,11 +347,11 @@ int upload_plan(DeviceTables *dt, int dtype, const PackedPlan &plan, hipStream_t
 }
 
 void free_tables(DeviceTables *dt) {
-    if (dt->stage_ev_valid) hipEventSynchronize(dt->stage_ev);
-    if (dt->stage_ev) hipEventDestroy(dt->stage_ev);
-    if (dt->d_ops) hipFree(dt->d_ops);
-    if (dt->d_coefs) hipFree(dt->d_coefs);
-    if (dt->h_stage) hipHostFree(dt->h_stage);
+    if (dt->stage_ev_valid) (void)hipEventSynchronize(dt->stage_ev);
+    if (dt->stage_ev) (void)hipEventDestroy(dt->stage_ev);
+    if (dt->d_ops) (void)hipFree(dt->d_ops);
+    if (dt->d_coefs) (void)hipFree(dt->d_coefs);
+    if (dt->h_stage) (void)hipHostFree(dt->h_stage);
     *dt = DeviceTables{};
 }
 
@@ -507,20 +507,20 @@ int qsim_create(int n, int dtype, void *dev_buf, size_t buf_bytes, void *hip_str
 
 int qsim_destroy(qsim_h h) {
     if (!h) return QSIM_E_ARG;
-    hipStreamSynchronize(h->stream);
+    (void)hipStreamSynchronize(h->stream);
     free_tables(&h->tables);
-    if (h->d_red) hipFree(h->d_red);
-    if (h->d_small) hipFree(h->d_small);
-    if (h->d_masks) hipFree(h->d_masks);
-    if (h->d_scan) hipFree(h->d_scan);
-    if (h->h_out) hipHostFree(h->h_out);
+    if (h->d_red) (void)hipFree(h->d_red);
+    if (h->d_small) (void)hipFree(h->d_small);
+    if (h->d_masks) (void)hipFree(h->d_masks);
+    if (h->d_scan) (void)hipFree(h->d_scan);
+    if (h->h_out) (void)hipHostFree(h->h_out);
     delete h;
     return QSIM_OK;
 }
 
 int qsim_set_stream(qsim_h h, void *st) {
     if (!h) return QSIM_E_ARG;
-    hipStreamSynchronize(h->stream);
+    (void)hipStreamSynchronize(h->stream);
     h->stream = (hipStream_t)st;
     return QSIM_OK;
 }
@@ -584,8 +584,8 @@ int qsim_run(qsim_h h, qsim_prog p) {
 
 int qsim_program_graph(qsim_prog p, qsim_h h, int enable) {
     if (!p || !h || h->n != p->n || h->dtype != p->dtype) return QSIM_E_ARG;
-    if (p->graph_exec) { hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
-    if (p->graph) { hipGraphDestroy(p->graph); p->graph = nullptr; }
+    if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
+    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
     p->graph_buf = nullptr;
     if (!enable || p->c.plan.ops.empty()) return QSIM_OK;
     hipStream_t cs;
@@ -600,10 +600,10 @@ int qsim_program_graph(qsim_prog p, qsim_h h, int enable) {
             p->graph = g;
             rc = hip_rc(hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0));
         } else if (g) {
-            hipGraphDestroy(g);
+            (void)hipGraphDestroy(g);
         }
     }
-    hipStreamDestroy(cs);
+    (void)hipStreamDestroy(cs);
     if (!rc) p->graph_buf = h->buf;
     return rc;
 }
@@ -661,10 +661,10 @@ int qsim_program_stats(qsim_prog p, qsim_apply_stats *out) {
 
 int qsim_program_destroy(qsim_prog p) {
     if (!p) return QSIM_E_ARG;
-    hipDeviceSynchronize();
-    if (p->graph_exec) hipGraphExecDestroy(p->graph_exec);
-    if (p->graph) hipGraphDestroy(p->graph);
-    for (hipEvent_t e : p->events) hipEventDestroy(e);
+    (void)hipDeviceSynchronize();
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
     free_tables(&p->dt);
     delete p;
     return QSIM_OK;
@@ -879,12 +879,12 @@ int qsim_autotune(qsim_h h, const qsim_gate *g, size_t ng, const double *mats, c
         if ((rc = upload_plan(&dt, h->dtype, c.plan, h->stream))) break;
         // warm, then time one run
         if ((rc = enqueue_passes(c, dt, h->dtype, h->buf, h->stream, false))) break;
-        hipEventRecord(e0, h->stream);
+        (void)hipEventRecord(e0, h->stream);
         if ((rc = enqueue_passes(c, dt, h->dtype, h->buf, h->stream, false))) break;
-        hipEventRecord(e1, h->stream);
+        (void)hipEventRecord(e1, h->stream);
         if ((rc = hip_rc(hipEventSynchronize(e1)))) break;
         float ms = 0;
-        hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
         const double ns = 1e6 * double(ms) / double(std::max<int64_t>(1, c.stats.input_gates));
         if (ns < best_ns) {
             best_ns = ns;
@@ -892,8 +892,8 @@ int qsim_autotune(qsim_h h, const qsim_gate *g, size_t ng, const double *mats, c
         }
     }
     free_tables(&dt);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (!rc) rc = qk::launch_init_zero(h->dtype, h->buf, 0, 1, h->n, h->stream);
     if (!rc) rc = hip_rc(hipStreamSynchronize(h->stream));
     if (ns_per_gate) *ns_per_gate = best_ns;

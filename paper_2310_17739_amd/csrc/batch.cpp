@@ -34,7 +34,7 @@ int dalloc(P **p, size_t bytes) {
 
 template <typename P>
 void dfree(P *&p) {
-    if (p) hipFree((void *)p);
+    if (p) (void)hipFree((void *)p);
     p = nullptr;
 }
 
@@ -389,10 +389,10 @@ int qsim_batch_run(qsim_batch_h b, void *hip_stream) {
                 b->graph = g;
                 rc = hip_ok(hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0), "graph instantiate");
             } else if (g) {
-                hipGraphDestroy(g);
+                (void)hipGraphDestroy(g);
             }
         }
-        hipStreamDestroy(cs);
+        (void)hipStreamDestroy(cs);
         if (rc) return rc;
     }
     return hip_ok(hipGraphLaunch(b->graph_exec, st), "graph launch");
@@ -460,9 +460,9 @@ int qsim_batch_info_get(qsim_batch_h b, qsim_batch_info *out) {
 
 int qsim_batch_destroy(qsim_batch_h b) {
     if (!b) return QSIM_E_ARG;
-    hipDeviceSynchronize();
-    if (b->graph_exec) hipGraphExecDestroy(b->graph_exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    (void)hipDeviceSynchronize();
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     for (Group &G : b->groups) free_group(G);
     delete b;
     return QSIM_OK;

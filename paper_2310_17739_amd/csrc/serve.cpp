@@ -112,7 +112,7 @@ struct Slot {
 
 int grow_dev(void **p, size_t *cap, size_t need) {
     if (need <= *cap) return QSIM_OK;
-    if (*p) hipFree(*p);
+    if (*p) (void)hipFree(*p);
     *p = nullptr;
     *cap = 0;
     size_t sz = std::max<size_t>(need + need / 4, 4096);
@@ -124,7 +124,7 @@ int grow_dev(void **p, size_t *cap, size_t need) {
 
 int grow_pinned(void **p, size_t *cap, size_t need) {
     if (need <= *cap) return QSIM_OK;
-    if (*p) hipHostFree(*p);
+    if (*p) (void)hipHostFree(*p);
     *p = nullptr;
     *cap = 0;
     size_t sz = std::max<size_t>(need + need / 4, 4096);
@@ -177,7 +177,7 @@ void finish(qsim_server *s, Request *r, int status, double norm, double expval) 
 }
 
 void worker_loop(qsim_server *s) {
-    hipSetDevice(s->device);
+    (void)hipSetDevice(s->device);
     const qsim_fuse_opts *fo = s->opt.fuse.level > 0 ? &s->opt.fuse : nullptr;
     for (;;) {
         Request *r;
@@ -269,7 +269,7 @@ void retire(qsim_server *s, Slot &sl) {
 }
 
 void scheduler_loop(qsim_server *s) {
-    hipSetDevice(s->device);
+    (void)hipSetDevice(s->device);
     for (;;) {
         bool progressed = false;
         // retire finished slots
@@ -314,7 +314,7 @@ void scheduler_loop(qsim_server *s) {
             free_slot->req = r;
             const int rc = launch_request(s, *free_slot, r);
             if (rc) {
-                hipStreamSynchronize(free_slot->st);
+                (void)hipStreamSynchronize(free_slot->st);
                 free_slot->req = nullptr;
                 {
                     std::lock_guard<std::mutex> lk(s->mu);
@@ -353,7 +353,7 @@ int qsim_server_create(const qsim_server_opts *opt, qsim_server_h *out) {
     qsim_server *s = new (std::nothrow) qsim_server;
     if (!s) return QSIM_E_NOMEM;
     s->opt = *opt;
-    hipGetDevice(&s->device);
+    (void)hipGetDevice(&s->device);
     hipError_t e = hipMalloc(&s->pool, opt->pool_bytes);
     if (e != hipSuccess) {
         qk::note_hip(e, "hipMalloc (server pool)");
@@ -449,16 +449,16 @@ int qsim_server_destroy(qsim_server_h s) {
         if (t.joinable()) t.join();
     if (s->scheduler.joinable()) s->scheduler.join();
     for (Slot &sl : s->slots) {
-        if (sl.st) hipStreamSynchronize(sl.st);
+        if (sl.st) (void)hipStreamSynchronize(sl.st);
         free_tables(&sl.dt);
-        if (sl.d_red) hipFree(sl.d_red);
-        if (sl.d_masks) hipFree(sl.d_masks);
-        if (sl.h_out) hipHostFree(sl.h_out);
-        if (sl.done) hipEventDestroy(sl.done);
-        if (sl.st) hipStreamDestroy(sl.st);
+        if (sl.d_red) (void)hipFree(sl.d_red);
+        if (sl.d_masks) (void)hipFree(sl.d_masks);
+        if (sl.h_out) (void)hipHostFree(sl.h_out);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.st) (void)hipStreamDestroy(sl.st);
     }
     for (Request *r : s->waiting) delete r;
-    if (s->pool) hipFree(s->pool);
+    if (s->pool) (void)hipFree(s->pool);
     delete s;
     return QSIM_OK;
 }
