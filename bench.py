@@ -105,23 +105,64 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
 
 
-def copy_rate_gbs(n_elems, dtype, reps=20):
-    """Rate of a plain device copy of a buffer of n_elems elements (bytes read
-    plus bytes written, per second): the ceiling a pass over a state of the
-    same size can reach."""
+def copy_ceiling(qsim, buf, reps=200):
+    """Same-footprint ceilings of a tile pass over the state buffer `buf`,
+    from the library's streaming-copy kernel run in place (bytes read plus
+    bytes written per second, averaged over `reps` back-to-back launches):
+
+    * stable: every 64 KiB block goes to the same workgroup (and XCD) on
+      every launch, so a block written by one launch is read back from that
+      XCD's L2 by the next;
+    * rotated: each launch hands every block to the next workgroup, so
+      blocks move between XCDs from launch to launch, as the tiles of
+      successive passes over different qubit sets do;
+
+    each with plain and with non-temporal loads and stores."""
     import torch
-    src = torch.zeros(n_elems, dtype=dtype, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    b.record()
-    torch.cuda.synchronize()
-    nbytes = 2 * src.element_size() * n_elems
-    return nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    nbytes = buf.numel() * buf.element_size()
+    stream = torch.cuda.current_stream()
+    out = {}
+    for nt in (0, 1):
+        for rot in (0, 1):
+            for i in range(5):
+                qsim.qsim_stream_copy(buf, buf, flags=nt, rotate=i * rot)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for i in range(reps):
+                qsim.qsim_stream_copy(buf, buf, flags=nt, rotate=i * rot)
+            b.record(stream)
+            torch.cuda.synchronize()
+            out[("nt_" if nt else "plain_") + ("rotated" if rot else "stable")] = \
+                2 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    out["best_stable"] = max(out["plain_stable"], out["nt_stable"])
+    out["best_rotated"] = max(out["plain_rotated"], out["nt_rotated"])
+    return out
+
+
+FIXTURE = os.path.join(ROOT, "tests", "golden", "cfg2_21q_50k_oracle.npz")
+
+
+def oracle_distance(W, psi, energy, H):
+    """Against the oracle's stored results for the 21-qubit, 50,000-exponential
+    circuit (written by tests/golden/make_cfg2_fixture.py, which runs only the
+    oracle): the estimate of ||psi/|psi| - phi/|phi|||^2 from 48 seeded
+    Gaussian probe overlaps (an upper bound of the infidelity of two unit
+    states, up to the estimate's spread) and |<H> - <H>_oracle| / sum|c|."""
+    import numpy as np
+    fx = np.load(FIXTURE)
+    a = np.asarray(psi, dtype=np.complex128)
+    na = np.sqrt(np.vdot(a, a).real)
+    nb = np.sqrt(float(fx["norm"]))
+    acc = 0.0
+    for k, r in enumerate(W.probe_vectors(int(fx["n"]), len(fx["probe"]))):
+        acc += abs(np.vdot(r, a) / na - fx["probe"][k] / nb) ** 2
+    d2 = acc / (2.0 * len(fx["probe"]))
+    idx = fx["sample_idx"]
+    amp = np.abs(a[idx] / na - fx["sample_amp"] / nb).max()
+    return {"distance2_estimate": d2, "probes": int(len(fx["probe"])),
+            "max_sampled_amplitude_error": float(amp),
+            "dexpval_over_sum_abs_c": abs(energy - float(fx["energy"])) / float(np.abs(H["coeff"]).sum()),
+            "oracle_energy": float(fx["energy"])}
 
 
 def run_trajectories(qsim, W, ntraj=1024, rounds=500):
@@ -177,8 +218,10 @@ def run_batched(qsim, W, n_circuits=4096, n_exp=500, sample_one_at_a_time=48):
     t0 = time.perf_counter()
     b = qsim.Batch(groups, dtype="complex64", use_graph=True)
     create_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
     b.qsim_batch_run()
     torch.cuda.synchronize()
+    first_s = time.perf_counter() - t0
     times = []
     for _ in range(3):
         t0 = time.perf_counter()
@@ -191,29 +234,46 @@ def run_batched(qsim, W, n_circuits=4096, n_exp=500, sample_one_at_a_time=48):
     info = b.qsim_batch_info()
     b.close()
     best = min(times)
-    # one circuit at a time, complex128: compile (bind angles on host, fuse,
-    # plan), run, <H>
+    # one circuit at a time, complex128, on a seeded sample: each circuit is
+    # compiled (angles bound on the host, fusion, plan) and then run with
+    # its <H>; compile and device time are kept apart so that both sides
+    # can be compared with and without their host preparation
     rng = np.random.default_rng(11)
     pick = rng.choice(n_circuits, size=min(sample_one_at_a_time, n_circuits), replace=False)
     diffs = []
+    compile_s = run_s = 0.0
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     for c in pick:
         w = int(widths[c])
         g, H = tmpl[w]
+        t0 = time.perf_counter()
+        prog = qsim.Program(w, g, "complex128", params=thetas[c])
+        t1 = time.perf_counter()
         sv = qsim.StateVector(w, "complex128")
-        sv.qsim_apply(g, params=thetas[c])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        prog.qsim_run(sv)
         e = sv.qsim_expval(H)
+        t3 = time.perf_counter()
+        compile_s += t1 - t0
+        run_s += t3 - t2
         diffs.append(abs(e - ev[c]) / np.abs(H["coeff"]).sum())
+        prog.close()
         sv.close()
-    torch.cuda.synchronize()
-    one_s = (time.perf_counter() - t0) / len(pick)
+    one_run = run_s / len(pick)
+    one_all = (run_s + compile_s) / len(pick)
     return {"workload": f"{n_circuits} circuits, widths U{{10..20}}, {n_exp} exponentials each, own angles, "
                         "complex64 + FP64 <H>, one HIP-graph launch",
             "circuits_per_s": n_circuits / best, "seconds": best, "create_s": create_s,
+            "first_run_s": first_s,
+            "circuits_per_s_with_create": n_circuits / (create_s + first_s),
             "state_bytes": info["state_bytes"], "passes": info["passes"],
-            "one_at_a_time_c128_circuits_per_s": 1.0 / one_s,
-            "speedup_vs_one_at_a_time_c128": (n_circuits / best) * one_s,
+            "tuned_width": info.get("tuned_width"),
+            "one_at_a_time_c128_circuits_per_s": 1.0 / one_run,
+            "one_at_a_time_c128_circuits_per_s_with_compile": 1.0 / one_all,
+            "one_at_a_time_sample": int(len(pick)),
+            "speedup_vs_one_at_a_time_c128": (n_circuits / best) * one_run,
+            "speedup_with_host_preparation_on_both_sides": (n_circuits / (create_s + first_s)) * one_all,
             "max_rel_dexpval_vs_c128": float(max(diffs))}
 
 
@@ -377,6 +437,7 @@ def run_wide_job(qsim, W, n=30, n_exp=40000):
         torch.cuda.synchronize()
         return 2 * src.numel() * src.element_size() / ((time.perf_counter() - c0) / 3) / 1e9
 
+    ceil = copy_ceiling(qsim, sv.tensor.view(torch.int64), reps=3)
     copy_before = copy_rate()
     sv.qsim_init_zero()
     torch.cuda.synchronize()
@@ -394,8 +455,9 @@ def run_wide_job(qsim, W, n=30, n_exp=40000):
     return {"workload": f"{n} qubits, {n_exp} exponentials ({st['input_gates']} gates), complex64",
             "passes": st["passes"], "tile_qubits": st["tile_qubits"], "seconds": dt,
             "gates_per_s": st["input_gates"] / dt, "avg_pass_ms": 1e3 * dt / st["passes"], "pass_GBps": gbs,
-            "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "copy_GBps_before": copy_before,
-            "copy_GBps_after": copy_after, "frac_of_copy_before": gbs / copy_before, "norm": nrm}
+            "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "stream_copy_GBps": ceil,
+            "frac_of_stream_copy": gbs / max(ceil["best_stable"], ceil["best_rotated"]),
+            "torch_copy_GBps_before": copy_before, "torch_copy_GBps_after": copy_after, "norm": nrm}
 
 
 def main():
@@ -412,8 +474,10 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy five times (a known byte count for "
                          "scaling memory counters)")
-    ap.add_argument("--forms", default="", help="comma list of extra forms to run: "
-                    "trajectories,batched,served,mma,wide (or 'all')")
+    ap.add_argument("--forms", default="batched,served,mma,wide",
+                    help="comma list of extra forms to run: trajectories,batched,served,mma,wide "
+                         "(or 'all'; '' or --no-forms for none)")
+    ap.add_argument("--no-forms", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no "
@@ -477,6 +541,11 @@ def main():
         pass_bytes = 2 * elem * (1 << n)
         res = {"dtype": dtype, "ms_per_step": ms_step, "gates_per_s": st["input_gates"] / (dt / args.steps),
                "compile_s": compile_s, "stats": st, "energy": energy, "norm": sv.qsim_norm()}
+        # a circuit run once: host compile (fusion + plan) plus one device run
+        res["gates_per_s_with_compile"] = st["input_gates"] / (compile_s + dt / args.steps)
+        if n == 21 and args.n_exp == 50_000 and os.path.exists(FIXTURE):
+            log(f"[bench] {dtype}: final state against the oracle's stored results")
+            res["vs_oracle"] = oracle_distance(W, sv.qsim_get_state(), energy, H)
         if not args.graph:
             # average launch duration over the timed region: the program's
             # span divided by its launches (inter-launch gaps included)
@@ -485,10 +554,13 @@ def main():
             achieved = pass_bytes / (avg_ms * 1e-3) / 1e9
             res["program_ms_per_step"] = float(np.mean(prog_ms))
             res["avg_launch_us"] = avg_ms * 1e3
-            copy_gbs = copy_rate_gbs(1 << n, torch.complex128 if elem == 16 else torch.complex64)
+            ceil = copy_ceiling(qsim, sv.tensor.view(torch.int64))
+            copy_gbs = max(ceil["best_stable"], ceil["best_rotated"])
             res["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dtype),
                                "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                               "copy_ceilings_GBps": ceil,
+                               "frac_of_rotated_copy": achieved / ceil["best_rotated"],
                                "kernel": f"k_tile<{'double' if elem == 16 else 'float'}, LE, "
                                          f"{os.environ.get('QSIM_TILE_THREADS') or (256 if elem == 16 else 512)}>",
                                "bytes_per_launch": pass_bytes, "launches_per_step": launches}
@@ -517,7 +589,7 @@ def main():
 
     main_res = measure(args.dtype)
     forms = {}
-    want = set(args.forms.split(",")) if args.forms else set()
+    want = set(args.forms.split(",")) if (args.forms and not args.no_forms) else set()
     if "all" in want:
         want = {"trajectories", "batched", "served", "mma", "wide"}
     for name, fn in (("trajectories", run_trajectories), ("batched", run_batched),
@@ -559,14 +631,16 @@ def main():
         "energy": main_res["energy"],
         "norm": main_res["norm"],
     }
-    for k in ("program_ms_per_step", "avg_launch_us", "per_pass_kernel_us", "alu", "lds"):
+    for k in ("program_ms_per_step", "avg_launch_us", "per_pass_kernel_us", "alu", "lds", "vs_oracle",
+              "gates_per_s_with_compile"):
         if k in main_res:
             out[k] = main_res[k]
     if forms:
         out["forms"] = forms
     if other is not None:
         out["other_dtype"] = {k: other[k] for k in ("dtype", "ms_per_step", "gates_per_s", "energy")}
-        for k in ("roofline", "avg_launch_us", "per_pass_kernel_us", "alu", "lds"):
+        for k in ("roofline", "avg_launch_us", "per_pass_kernel_us", "alu", "lds", "vs_oracle",
+                  "gates_per_s_with_compile", "compile_s"):
             if k in other:
                 out["other_dtype"][k] = other[k]
     print(json.dumps(out), flush=True)

@@ -151,14 +151,17 @@ int qsim_set_stream(qsim_h h, void *hip_stream);
 int qsim_init_zero(qsim_h h);   /* |0...0>, asynchronous */
 
 /* Apply U_{m-1} ... U_0 (Section 3.2) given as gate records.  MAT records
- * read their matrices from `mats` (interleaved complex128); records with
- * slot >= 0 read theta[0] from `params`.  BARRIER records fence fusion.
+ * read their matrices from `mats` (interleaved complex128, n_mats complex
+ * entries; a k-qubit record needs mat_off + 4^k <= n_mats); records with
+ * slot >= 0 read theta[0] from `params` (slot < n_params).  Both arrays stay
+ * the caller's and are read before the call returns.  BARRIER records fence
+ * fusion.
  * MEASURE / RESET / ASSERT0 records are rejected (QSIM_E_UNSUPPORTED): use
  * the calls below, or qsim_batch_* for programs with device-side decisions.
  * Errors: QSIM_E_QUBIT, QSIM_E_ARG, QSIM_E_UNSUPPORTED, QSIM_E_NOMEM,
  * QSIM_E_HIP.  Asynchronous. */
-int qsim_apply(qsim_h h, const qsim_gate *g, size_t ng, const double *mats,
-               const double *params, const qsim_fuse_opts *opt);
+int qsim_apply(qsim_h h, const qsim_gate *g, size_t ng, const double *mats, size_t n_mats,
+               const double *params, size_t n_params, const qsim_fuse_opts *opt);
 int qsim_last_stats(qsim_h h, qsim_apply_stats *out);
 
 /* Born-rule measurement of qubit q (Section 4.3): P0, P1 are reduced in
@@ -167,27 +170,46 @@ int qsim_last_stats(qsim_h h, qsim_apply_stats *out);
  * Writes the outcome and its probability.  Synchronous. */
 int qsim_measure(qsim_h h, int q, double u, int *outcome, double *p_outcome);
 
-/* Measurement assertion (Section 4.3): if P(q = 0) > 0 the outcome is taken
- * as 0, the state is projected and renormalised and P(q = 0) is written;
- * otherwise QSIM_E_ZERO_PROB and the state is untouched. */
-int qsim_measure_assert(qsim_h h, int q, double *p_zero);
+/* Measurement assertion (Section 4.3).  The paper asserts that the
+ * ancilla reads 0 (want = 0); want = 1 asserts the other outcome, as a
+ * filter step that keeps the |1> branch would.  If P(q = want) > 0 the
+ * outcome is taken as `want`, the state is projected and renormalised (FP64
+ * scale) and P(q = want) / (P0 + P1) is written to *p_want; otherwise
+ * QSIM_E_ZERO_PROB and the state is untouched.  want not in {0, 1}:
+ * QSIM_E_ARG.  Synchronous. */
+int qsim_measure_assert(qsim_h h, int q, int want, double *p_want);
 
 /* Reset (Listing 1): identity if qubit q is |0>, X if it is |1>;
  * QSIM_E_NOT_DEFINITE (state untouched) if it is in superposition. */
 int qsim_reset(qsim_h h, int q);
 
-/* <psi|H|psi> / <psi|psi> for H = sum_k coeff_k P_k, accumulated in FP64
- * with a fixed reduction order.  Masks must be < 2^n. */
+/* Energy of a Hamiltonian given as a Pauli sum: the energies of Table 7 are
+ * such expectation values of the state the circuit prepares (Section 2:
+ * H written as a sum of Pauli strings).  Computes <psi|H|psi> / <psi|psi>
+ * for H = sum_k coeff_k P_k with P|x> = i^{#Y} (-1)^{popcount(x & zmask)}
+ * |x ^ xmask> (a Y on qubit q sets both mask bits), accumulated in FP64 with
+ * a fixed reduction order.  t: nt caller-owned terms; masks must be < 2^n
+ * and coefficients finite (QSIM_E_ARG).  Writes one double.  Synchronous. */
 int qsim_expval(qsim_h h, const qsim_pauli *t, size_t nt, double *out);
 
-/* Marginal probabilities of qubits qs[0..nqs-1] (nqs <= 12), normalised by
- * <psi|psi>: out[j], j = sum_i bit(qs[i]) 2^i, 2^nqs doubles. */
+/* Born-rule marginal distribution of a qubit subset (Section 4.3: after
+ * the assertions, the final state's probabilities are what the shots are
+ * drawn from).  out[j], j = sum_i bit(qs[i]) 2^i, is the weight of the
+ * basis states with those bits, normalised by <psi|psi> and reduced in FP64.
+ * qs: nqs distinct qubits (0 <= nqs <= 12; QSIM_E_QUBIT otherwise); out:
+ * 2^nqs caller-owned doubles.  QSIM_E_ZERO_PROB for the zero vector.
+ * Synchronous. */
 int qsim_probs(qsim_h h, const int *qs, int nqs, double *out);
 
-/* <psi|psi> in FP64. */
+/* <psi|psi> in FP64: the squared norm that renormalisation after a
+ * projective measurement divides by (Section 4.3); for complex64 states it
+ * also shows the rounding drift of the sweeps.  Synchronous. */
 int qsim_norm(qsim_h h, double *out);
 
-/* Copy the state to / from host memory (2^n elements of the state dtype). */
+/* Copy the 2^n amplitudes of the state vector (Section 3.2: amplitude i
+ * holds the coefficient of basis state i, qubit q being bit q of i) to or
+ * from host memory: 2^n caller-owned elements of the state dtype
+ * (interleaved re, im).  Synchronous. */
 int qsim_get_state(qsim_h h, void *host_dst);
 int qsim_set_state(qsim_h h, const void *host_src);
 
@@ -200,7 +222,8 @@ typedef struct qsim_program *qsim_prog;
 
 /* Compile and upload (synchronous).  Same inputs and errors as qsim_apply. */
 int qsim_compile(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
-                 const double *params, const qsim_fuse_opts *opt, qsim_prog *out);
+                 size_t n_mats, const double *params, size_t n_params,
+                 const qsim_fuse_opts *opt, qsim_prog *out);
 /* Enqueue the program's passes on the handle's stream (asynchronous).
  * QSIM_E_ARG if the width or dtype differ from the handle's. */
 int qsim_run(qsim_h h, qsim_prog p);
@@ -234,6 +257,7 @@ typedef struct qsim_batch_group {
     const qsim_gate *g;      /* the shared program */
     size_t ng;
     const double *mats;      /* MAT pool (complex128), or NULL */
+    size_t n_mats;           /* complex entries in the pool */
     const double *params;    /* n_states x n_params angles read by records with
                                 slot >= 0 (RX, RY, RZ, RXX, RZZ), or NULL */
     int32_t n_params;
@@ -357,6 +381,22 @@ int qsim_server_destroy(qsim_server_h s);
  * uses 8 * 2^n bytes of device scratch, allocated on first use. */
 int qsim_sample(qsim_h h, const double *uniforms, size_t m, uint64_t *out);
 
+/* ------------------------------------------------------ copy ceiling */
+
+/* Not a step of the method: the same-footprint memory ceiling that the
+ * benchmark sets beside a tile pass.  Copies `bytes` (a multiple of 16)
+ * from src to dst, both device pointers; dst == src is allowed and makes an
+ * in-place pass that reads and writes every byte once, the traffic of one
+ * tile pass over a state of that size.  Workgroups of 256 threads each move
+ * a 64 KiB block (16 loads of 16 bytes per thread in flight, then 16
+ * stores), the tile kernel's shape for complex128.  flags bit 0: non-temporal
+ * loads and stores.  `rotate` offsets the block a workgroup takes; changing
+ * it between calls moves every block to another workgroup and XCD, as a tile
+ * pass over a new qubit set does.  Asynchronous on hip_stream.  Errors:
+ * QSIM_E_ARG (null pointer, size not a multiple of 16, unknown flag). */
+int qsim_stream_copy(void *dst, const void *src, size_t bytes, int flags, uint32_t rotate,
+                     void *hip_stream);
+
 /* ----------------------------------------------------------- autotune */
 
 /* Pick fusion width, per-operator cost, tile qubits and contiguous low
@@ -365,9 +405,9 @@ int qsim_sample(qsim_h h, const double *uniforms, size_t m, uint64_t *out);
  * h's state, timed with HIP events; the fastest per input gate wins.  The
  * state is left as |0...0>.  Writes the chosen options (level 5) and their
  * time per input gate in ns.  Synchronous. */
-int qsim_autotune(qsim_h h, const qsim_gate *g, size_t ng, const double *mats,
-                  const double *params, size_t prefix_gates, qsim_fuse_opts *best,
-                  double *ns_per_gate);
+int qsim_autotune(qsim_h h, const qsim_gate *g, size_t ng, const double *mats, size_t n_mats,
+                  const double *params, size_t n_params, size_t prefix_gates,
+                  qsim_fuse_opts *best, double *ns_per_gate);
 
 /* ------------------------------------------------------- host-only tools */
 
@@ -378,8 +418,8 @@ int qsim_autotune(qsim_h h, const qsim_gate *g, size_t ng, const double *mats,
  * out_mats (interleaved doubles).  Capacities in operators / doubles;
  * QSIM_E_CAPACITY if too small.  `counts` (6 entries, may be NULL) receives
  * the operator count after each fusion level. */
-int qsim_debug_fuse(int n, const qsim_gate *g, size_t ng, const double *mats,
-                    const double *params, const qsim_fuse_opts *opt,
+int qsim_debug_fuse(int n, const qsim_gate *g, size_t ng, const double *mats, size_t n_mats,
+                    const double *params, size_t n_params, const qsim_fuse_opts *opt,
                     int32_t *out_k, int32_t *out_qubits, double *out_mats,
                     size_t cap_ops, size_t cap_doubles, size_t *n_ops,
                     int64_t *counts);
@@ -419,13 +459,14 @@ int qsim_parse_qasm(const char *text, size_t len, qsim_gate *out, size_t cap, si
  * psi: 2^n interleaved complex128 values, updated in place (caller-owned).
  * Errors: as qsim_compile, and QSIM_E_ARG for n > 24 or psi == NULL. */
 int qsim_debug_emulate(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
-                       const double *params, const qsim_fuse_opts *opt, double *psi);
+                       size_t n_mats, const double *params, size_t n_params,
+                       const qsim_fuse_opts *opt, double *psi);
 
 /* Host-only: number of full-state passes the planner makes for the fused
  * circuit (same inputs as qsim_debug_fuse), for n qubits and dtype. */
 int qsim_debug_plan(int n, int dtype, const qsim_gate *g, size_t ng,
-                    const double *mats, const double *params,
-                    const qsim_fuse_opts *opt, qsim_apply_stats *out);
+                    const double *mats, size_t n_mats, const double *params,
+                    size_t n_params, const qsim_fuse_opts *opt, qsim_apply_stats *out);
 
 const char *qsim_strerror(int status);
 /* Text of the last failed HIP call on this thread (empty if none). */

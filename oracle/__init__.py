@@ -184,8 +184,9 @@ def sample(n, psi, uniforms) -> np.ndarray:
 
 
 def infidelity(a, b) -> float:
-    """1 - |<a|b>|^2 / (<a|a><b|b>), evaluated in extended precision where
-    available so that values near 1e-16 are meaningful."""
+    """1 - |<a|b>|^2 / (<a|a><b|b>) in float64 (the reading of infidelity
+    for states that need not have unit norm).  Rounding limits its
+    resolution to about 1e-16 times the dimension's square root."""
     a = np.asarray(a, dtype=np.complex128)
     b = np.asarray(b, dtype=np.complex128)
     ov = np.vdot(a, b)

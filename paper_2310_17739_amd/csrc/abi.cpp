@@ -188,13 +188,13 @@ int validate_plan(int n, int dtype, const Compiled &c) {
     return QSIM_OK;
 }
 
-int compile_circuit(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
-                    const double *params, const qsim_fuse_opts *opt, Compiled *out) {
-    return compile_program(n, dtype, g, ng, mats, params, false, false, 0, opt, out);
+int compile_circuit(int n, int dtype, const qsim_gate *g, size_t ng, const GateInputs &in,
+                    const qsim_fuse_opts *opt, Compiled *out) {
+    return compile_program(n, dtype, g, ng, in, false, false, 0, opt, out);
 }
 
-int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
-                    const double *params, bool keep_params, bool allow_meas, int max_params,
+int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const GateInputs &in,
+                    bool keep_params, bool allow_meas, int max_params,
                     const qsim_fuse_opts *opt, Compiled *out) {
     double t0 = now_seconds();
     FuseConfig fc;
@@ -202,7 +202,7 @@ int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const doubl
     default_configs(n, dtype, opt, &fc, &pc);
     fc.max_params = keep_params ? std::max(1, std::min(max_params, 3)) : 0;
     Lowered L;
-    int rc = lower(n, g, ng, mats, params, keep_params, allow_meas, &L);
+    int rc = lower(n, g, ng, in, keep_params, allow_meas, &L);
     if (rc) return rc;
     int64_t counts[6];
     fuse(n, &L, fc, counts);
@@ -525,18 +525,24 @@ int qsim_set_stream(qsim_h h, void *st) {
     return QSIM_OK;
 }
 
+int qsim_stream_copy(void *dst, const void *src, size_t bytes, int flags, uint32_t rotate,
+                     void *hip_stream) {
+    if (!dst || !src || bytes % 16 || (flags & ~1)) return QSIM_E_ARG;
+    return qk::launch_stream_copy(dst, src, bytes, (flags & 1) != 0, rotate, (hipStream_t)hip_stream);
+}
+
 int qsim_init_zero(qsim_h h) {
     if (!h) return QSIM_E_ARG;
     return qk::launch_init_zero(h->dtype, h->buf, 0, 1, h->n, h->stream);
 }
 
-int qsim_apply(qsim_h h, const qsim_gate *g, size_t ng, const double *mats, const double *params,
-               const qsim_fuse_opts *opt) {
+int qsim_apply(qsim_h h, const qsim_gate *g, size_t ng, const double *mats, size_t n_mats,
+               const double *params, size_t n_params, const qsim_fuse_opts *opt) {
     if (!h || (ng && !g)) return QSIM_E_ARG;
     Compiled c;
     int rc;
     try {
-        rc = compile_circuit(h->n, h->dtype, g, ng, mats, params, opt, &c);
+        rc = compile_circuit(h->n, h->dtype, g, ng, GateInputs{mats, n_mats, params, n_params}, opt, &c);
     } catch (const std::bad_alloc &) {
         return QSIM_E_NOMEM;
     }
@@ -550,7 +556,8 @@ int qsim_apply(qsim_h h, const qsim_gate *g, size_t ng, const double *mats, cons
 }
 
 int qsim_compile(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
-                 const double *params, const qsim_fuse_opts *opt, qsim_prog *out) {
+                 size_t n_mats, const double *params, size_t n_params, const qsim_fuse_opts *opt,
+                 qsim_prog *out) {
     if (!out || n < 1 || n > kMaxQubits || (dtype != QSIM_C64 && dtype != QSIM_C128) || (ng && !g))
         return QSIM_E_ARG;
     int rc = qk::init_kernels();
@@ -560,7 +567,7 @@ int qsim_compile(int n, int dtype, const qsim_gate *g, size_t ng, const double *
     p->n = n;
     p->dtype = dtype;
     try {
-        rc = compile_circuit(n, dtype, g, ng, mats, params, opt, &p->c);
+        rc = compile_circuit(n, dtype, g, ng, GateInputs{mats, n_mats, params, n_params}, opt, &p->c);
     } catch (const std::bad_alloc &) {
         rc = QSIM_E_NOMEM;
     }
@@ -694,16 +701,17 @@ int qsim_measure(qsim_h h, int q, double u, int *outcome, double *p_outcome) {
     return QSIM_OK;
 }
 
-int qsim_measure_assert(qsim_h h, int q, double *p_zero) {
-    if (!h || !p_zero) return QSIM_E_ARG;
+int qsim_measure_assert(qsim_h h, int q, int want, double *p_want) {
+    if (!h || !p_want || (want != 0 && want != 1)) return QSIM_E_ARG;
     if (q < 0 || q >= h->n) return QSIM_E_QUBIT;
     double P0, P1;
     int rc = weights01(h, q, &P0, &P1);
     if (rc) return rc;
-    if (!(P0 > 0.0)) return QSIM_E_ZERO_PROB;
-    rc = qk::launch_collapse(h->dtype, h->buf, h->n, q, 0, 1.0 / std::sqrt(P0), h->stream);
+    const double kept = want ? P1 : P0;
+    if (!(kept > 0.0)) return QSIM_E_ZERO_PROB;
+    rc = qk::launch_collapse(h->dtype, h->buf, h->n, q, want, 1.0 / std::sqrt(kept), h->stream);
     if (rc) return rc;
-    *p_zero = P0 / (P0 + P1);
+    *p_want = kept / (P0 + P1);
     return QSIM_OK;
 }
 
@@ -838,8 +846,9 @@ int qsim_set_state(qsim_h h, const void *src) {
     return hip_rc(hipStreamSynchronize(h->stream));
 }
 
-int qsim_autotune(qsim_h h, const qsim_gate *g, size_t ng, const double *mats, const double *params,
-                  size_t prefix_gates, qsim_fuse_opts *best, double *ns_per_gate) {
+int qsim_autotune(qsim_h h, const qsim_gate *g, size_t ng, const double *mats, size_t n_mats,
+                  const double *params, size_t n_params, size_t prefix_gates, qsim_fuse_opts *best,
+                  double *ns_per_gate) {
     if (!h || !best || (ng && !g)) return QSIM_E_ARG;
     if (prefix_gates == 0) prefix_gates = 20000;
     // the prefix ends at a whole number of records; barriers are kept
@@ -870,7 +879,7 @@ int qsim_autotune(qsim_h h, const qsim_gate *g, size_t ng, const double *mats, c
     for (const qsim_fuse_opts &o : cands) {
         Compiled c;
         try {
-            rc = compile_circuit(h->n, h->dtype, g, np, mats, params, &o, &c);
+            rc = compile_circuit(h->n, h->dtype, g, np, GateInputs{mats, n_mats, params, n_params}, &o, &c);
         } catch (const std::bad_alloc &) {
             rc = QSIM_E_NOMEM;
         }
@@ -900,8 +909,8 @@ int qsim_autotune(qsim_h h, const qsim_gate *g, size_t ng, const double *mats, c
     return rc;
 }
 
-int qsim_debug_fuse(int n, const qsim_gate *g, size_t ng, const double *mats, const double *params,
-                    const qsim_fuse_opts *opt, int32_t *out_k, int32_t *out_qubits,
+int qsim_debug_fuse(int n, const qsim_gate *g, size_t ng, const double *mats, size_t n_mats,
+                    const double *params, size_t n_params, const qsim_fuse_opts *opt, int32_t *out_k, int32_t *out_qubits,
                     double *out_mats, size_t cap_ops, size_t cap_doubles, size_t *n_ops,
                     int64_t *counts) {
     if (n < 1 || n > kMaxQubits || (ng && !g) || !n_ops) return QSIM_E_ARG;
@@ -913,7 +922,7 @@ int qsim_debug_fuse(int n, const qsim_gate *g, size_t ng, const double *mats, co
     int rc;
     int64_t cnt[6];
     try {
-        rc = lower(n, g, ng, mats, params, false, false, &L);
+        rc = lower(n, g, ng, GateInputs{mats, n_mats, params, n_params}, false, false, &L);
         if (rc) return rc;
         fuse(n, &L, fc, cnt);
     } catch (const std::bad_alloc &) {
@@ -963,12 +972,13 @@ int qsim_parse_qasm(const char *text, size_t len, qsim_gate *out, size_t cap, si
 }
 
 int qsim_debug_emulate(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
-                       const double *params, const qsim_fuse_opts *opt, double *psi) {
+                       size_t n_mats, const double *params, size_t n_params,
+                       const qsim_fuse_opts *opt, double *psi) {
     if (n < 1 || n > 24 || (dtype != QSIM_C64 && dtype != QSIM_C128) || !psi) return QSIM_E_ARG;
     Compiled c;
     int rc;
     try {
-        rc = compile_circuit(n, dtype, g, ng, mats, params, opt, &c);
+        rc = compile_circuit(n, dtype, g, ng, GateInputs{mats, n_mats, params, n_params}, opt, &c);
     } catch (const std::bad_alloc &) {
         return QSIM_E_NOMEM;
     }
@@ -1045,12 +1055,13 @@ int qsim_debug_emulate(int n, int dtype, const qsim_gate *g, size_t ng, const do
 }
 
 int qsim_debug_plan(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
-                    const double *params, const qsim_fuse_opts *opt, qsim_apply_stats *out) {
+                    size_t n_mats, const double *params, size_t n_params,
+                    const qsim_fuse_opts *opt, qsim_apply_stats *out) {
     if (n < 1 || n > kMaxQubits || (dtype != QSIM_C64 && dtype != QSIM_C128) || !out) return QSIM_E_ARG;
     Compiled c;
     int rc;
     try {
-        rc = compile_circuit(n, dtype, g, ng, mats, params, opt, &c);
+        rc = compile_circuit(n, dtype, g, ng, GateInputs{mats, n_mats, params, n_params}, opt, &c);
     } catch (const std::bad_alloc &) {
         return QSIM_E_NOMEM;
     }

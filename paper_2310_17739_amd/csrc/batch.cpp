@@ -155,7 +155,10 @@ int setup_group(Group &G, const qsim_batch_group &in, int dtype, const qsim_batc
     const size_t elem = elem_bytes(dtype);
     const bool param = in.params != nullptr && in.n_params > 0;
     const qsim_fuse_opts *fo = (opt.fuse.level > 0) ? &opt.fuse : nullptr;
-    int rc = compile_program(in.n, dtype, in.g, in.ng, in.mats, nullptr, param, true,
+    int rc = compile_program(in.n, dtype, in.g, in.ng,
+                             GateInputs{in.mats, in.mats ? in.n_mats : 0, nullptr,
+                                        param ? size_t(in.n_params) : 0},
+                             param, true,
                              opt.max_params > 0 ? opt.max_params : 2, fo, &G.c);
     if (rc) return rc;
     // every parameter slot and measurement slot must be inside its vector

@@ -211,8 +211,8 @@ void to_sorted(const int *qs, int k, const cd *src, int nblocks, Op *op) {
 
 }  // namespace
 
-int lower(int n, const qsim_gate *g, size_t ng, const double *mats, const double *params,
-          bool keep_params, bool allow_meas, Lowered *out) {
+int lower(int n, const qsim_gate *g, size_t ng, const GateInputs &in, bool keep_params,
+          bool allow_meas, Lowered *out) {
     out->ops.clear();
     out->op_epoch.clear();
     out->meas.clear();
@@ -256,10 +256,11 @@ int lower(int n, const qsim_gate *g, size_t ng, const double *mats, const double
         if (gi.slot >= 0) {
             if (keep_params) {
                 if (!is_half_angle_linear(gi.kind)) return QSIM_E_UNSUPPORTED;
+                if (size_t(gi.slot) >= in.n_params) return QSIM_E_ARG;
                 symbolic = true;
             } else {
-                if (!params) return QSIM_E_ARG;
-                th[0] = params[gi.slot];
+                if (!in.params || size_t(gi.slot) >= in.n_params) return QSIM_E_ARG;
+                th[0] = in.params[gi.slot];
             }
         }
         for (double v : th)
@@ -269,7 +270,8 @@ int lower(int n, const qsim_gate *g, size_t ng, const double *mats, const double
         op.orient = (k == 2 && gi.q[0] > gi.q[1]) ? 1 : 0;
         int d = 1 << k;
         if (gi.kind == QSIM_G_MAT) {
-            if (!mats) return QSIM_E_ARG;
+            if (!in.mats || size_t(gi.mat_off) + size_t(d) * d > in.n_mats) return QSIM_E_ARG;
+            const double *mats = in.mats;
             m.resize(size_t(d) * d);
             const double *src = mats + 2 * size_t(gi.mat_off);
             for (int e = 0; e < d * d; e++) {

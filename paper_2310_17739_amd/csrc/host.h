@@ -78,8 +78,17 @@ int parse_qasm(const char *text, size_t len, std::vector<qsim_gate> *out, int *n
 // ---- lowering (gates.cpp)
 // Returns QSIM_OK or an error; fills `out`.  Gate matrices are built in FP64.
 // Measurement records are accepted only with `allow_meas`.
-int lower(int n, const qsim_gate *g, size_t ng, const double *mats,
-          const double *params, bool keep_params, bool allow_meas, Lowered *out);
+// The caller's matrix pool and parameter vector with their lengths: a MAT
+// record needs mat_off + 4^k <= n_mats (complex entries), a record with
+// slot >= 0 needs slot < n_params.
+struct GateInputs {
+    const double *mats = nullptr;
+    size_t n_mats = 0;
+    const double *params = nullptr;
+    size_t n_params = 0;
+};
+int lower(int n, const qsim_gate *g, size_t ng, const GateInputs &in, bool keep_params,
+          bool allow_meas, Lowered *out);
 // Dense matrix of one gate record on its own qubits in record order.
 int gate_matrix(const qsim_gate &g, const double *theta, std::vector<cd> *m);
 

@@ -780,6 +780,38 @@ __global__ void __launch_bounds__(NT) k_collapse(Cx<T> *__restrict__ state, uint
     }
 }
 
+// ------------------------------------------------------- streaming copy
+// The same-footprint ceiling of a tile pass: workgroup b moves 64 KiB block
+// (b + rotate) mod nblocks of src to dst, 256 threads, 16 elements of 16
+// bytes each, all loads in flight before the first store (the tile kernel's
+// grid shape and access order for complex128).  dst may equal src: an
+// in-place pass then reads and writes every byte once, the traffic of one
+// tile pass.  Changing `rotate` between calls hands each block to another
+// workgroup, and so to another XCD's L2, as a tile pass over new qubits does.
+template <bool NTMP>
+__global__ void __launch_bounds__(256) k_stream_copy(const uint32_t *src, uint32_t *dst, uint64_t n16,
+                                                     uint32_t nblocks, uint32_t rotate) {
+    typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+    const U4 *s = reinterpret_cast<const U4 *>(src);
+    U4 *d = reinterpret_cast<U4 *>(dst);
+    const uint64_t blk = (uint64_t(blockIdx.x) + rotate) % nblocks;
+    const uint64_t base = blk * 4096 + threadIdx.x;
+    U4 v[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+        const uint64_t x = base + uint64_t(i) * 256;
+        if (x < n16) v[i] = NTMP ? __builtin_nontemporal_load(s + x) : s[x];
+    }
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+        const uint64_t x = base + uint64_t(i) * 256;
+        if (x < n16) {
+            if (NTMP) __builtin_nontemporal_store(v[i], d + x);
+            else d[x] = v[i];
+        }
+    }
+}
+
 // ---------------------------------------------------------- reductions
 struct MargArgs {
     int32_t n, nqs;
@@ -1171,6 +1203,22 @@ int launch_init_zero(int dtype, void *state, uint64_t sstride, uint32_t nstates,
         hipLaunchKernelGGL(k_init_zero<float>, grid, dim3(NT), 0, st, (Cx<float> *)state, sstride, len);
     else
         hipLaunchKernelGGL(k_init_zero<double>, grid, dim3(NT), 0, st, (Cx<double> *)state, sstride, len);
+    return check(hipGetLastError());
+}
+
+int launch_stream_copy(void *dst, const void *src, uint64_t bytes, bool nontemporal, uint32_t rotate,
+                       hipStream_t st) {
+    const uint64_t n16 = bytes / 16;
+    if (n16 == 0) return QSIM_OK;
+    const uint64_t nb = (n16 + 4095) / 4096;
+    if (nb > 0x7fffffffull) return QSIM_E_ARG;
+    const uint32_t nblocks = uint32_t(nb);
+    if (nontemporal)
+        hipLaunchKernelGGL(k_stream_copy<true>, dim3(nblocks), dim3(256), 0, st, (const uint32_t *)src,
+                           (uint32_t *)dst, n16, nblocks, rotate % nblocks);
+    else
+        hipLaunchKernelGGL(k_stream_copy<false>, dim3(nblocks), dim3(256), 0, st, (const uint32_t *)src,
+                           (uint32_t *)dst, n16, nblocks, rotate % nblocks);
     return check(hipGetLastError());
 }
 

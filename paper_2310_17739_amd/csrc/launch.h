@@ -100,6 +100,12 @@ int launch_blockscan(int dtype, const void *state, int n, double *cum, double *b
 int launch_addoff_search(double *cum, int n, const double *boff, const double *u, uint64_t m,
                          uint64_t *out, hipStream_t st);
 
+// Streaming copy of `bytes` (a multiple of 16) from src to dst (dst == src
+// allowed) in 64 KiB blocks, one workgroup each, block b handled by
+// workgroup (b - rotate) mod blocks; plain or non-temporal loads and stores.
+int launch_stream_copy(void *dst, const void *src, uint64_t bytes, bool nontemporal, uint32_t rotate,
+                       hipStream_t st);
+
 // |0...0> in every state of a batch.
 int launch_init_zero(int dtype, void *state, uint64_t sstride, uint32_t nstates, int n,
                      hipStream_t st);

@@ -40,13 +40,13 @@ size_t elem_bytes(int dtype);
 int env_int(const char *name, int dflt);
 int resident_max(int dtype);
 void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc, PlanConfig *pc);
-int compile_circuit(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
-                    const double *params, const qsim_fuse_opts *opt, Compiled *out);
+int compile_circuit(int n, int dtype, const qsim_gate *g, size_t ng, const GateInputs &in,
+                    const qsim_fuse_opts *opt, Compiled *out);
 // General form: keep_params keeps slot >= 0 angles symbolic (cos/sin basis
 // blocks, at most max_params per fused operator); allow_meas accepts
 // MEASURE / ASSERT0 / RESET records.
-int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const double *mats,
-                    const double *params, bool keep_params, bool allow_meas, int max_params,
+int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const GateInputs &in,
+                    bool keep_params, bool allow_meas, int max_params,
                     const qsim_fuse_opts *opt, Compiled *out);
 int validate_plan(int n, int dtype, const Compiled &c);
 int upload_plan(DeviceTables *dt, int dtype, const PackedPlan &plan, hipStream_t st);

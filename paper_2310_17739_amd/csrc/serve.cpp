@@ -191,7 +191,9 @@ void worker_loop(qsim_server *s) {
         int rc;
         try {
             rc = compile_circuit(r->n, s->opt.dtype, r->g.data(), r->g.size(),
-                                 r->mats.empty() ? nullptr : r->mats.data(), nullptr, fo, &r->c);
+                                 GateInputs{r->mats.empty() ? nullptr : r->mats.data(),
+                                            r->mats.size() / 2, nullptr, 0},
+                                 fo, &r->c);
         } catch (const std::bad_alloc &) {
             rc = QSIM_E_NOMEM;
         }

@@ -75,29 +75,30 @@ def _load():
         "qsim_destroy": ([P], I),
         "qsim_set_stream": ([P, P], I),
         "qsim_init_zero": ([P], I),
-        "qsim_apply": ([P, P, SZ, P, P, P], I),
+        "qsim_apply": ([P, P, SZ, P, SZ, P, SZ, P], I),
         "qsim_last_stats": ([P, P], I),
         "qsim_measure": ([P, I, D, P, P], I),
-        "qsim_measure_assert": ([P, I, P], I),
+        "qsim_measure_assert": ([P, I, I, P], I),
         "qsim_reset": ([P, I], I),
         "qsim_expval": ([P, P, SZ, P], I),
         "qsim_probs": ([P, P, I, P], I),
         "qsim_norm": ([P, P], I),
         "qsim_get_state": ([P, P], I),
         "qsim_set_state": ([P, P], I),
-        "qsim_debug_fuse": ([I, P, SZ, P, P, P, P, P, P, SZ, SZ, P, P], I),
+        "qsim_debug_fuse": ([I, P, SZ, P, SZ, P, SZ, P, P, P, P, SZ, SZ, P, P], I),
         "qsim_parse_qasm": ([C.c_char_p, SZ, P, SZ, P, P, P], I),
-        "qsim_compile": ([I, I, P, SZ, P, P, P, P], I),
+        "qsim_compile": ([I, I, P, SZ, P, SZ, P, SZ, P, P], I),
         "qsim_run": ([P, P], I),
         "qsim_program_graph": ([P, P, I], I),
         "qsim_run_timed": ([P, P], I),
         "qsim_program_kernel_ms": ([P, P, P], I),
         "qsim_program_stats": ([P, P], I),
         "qsim_program_destroy": ([P], I),
-        "qsim_debug_plan": ([I, I, P, SZ, P, P, P, P], I),
-        "qsim_debug_emulate": ([I, I, P, SZ, P, P, P, P], I),
-        "qsim_autotune": ([P, P, SZ, P, P, SZ, P, P], I),
+        "qsim_debug_plan": ([I, I, P, SZ, P, SZ, P, SZ, P, P], I),
+        "qsim_debug_emulate": ([I, I, P, SZ, P, SZ, P, SZ, P, P], I),
+        "qsim_autotune": ([P, P, SZ, P, SZ, P, SZ, SZ, P, P], I),
         "qsim_sample": ([P, P, SZ, P], I),
+        "qsim_stream_copy": ([P, P, SZ, I, C.c_uint32, P], I),
         "qsim_batch_create": ([P, I, P, P], I),
         "qsim_batch_run": ([P, P], I),
         "qsim_batch_results": ([P, I, P, P, P, P, P], I),
@@ -132,7 +133,7 @@ def _bind_optional(lib):
 
 class qsim_batch_group(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_states", C.c_int32), ("g", C.c_void_p), ("ng", C.c_size_t),
-                ("mats", C.c_void_p), ("params", C.c_void_p), ("n_params", C.c_int32),
+                ("mats", C.c_void_p), ("n_mats", C.c_size_t), ("params", C.c_void_p), ("n_params", C.c_int32),
                 ("uniforms", C.c_void_p), ("forced", C.c_void_p), ("n_slots", C.c_int32),
                 ("terms", C.c_void_p), ("n_terms", C.c_size_t), ("dev_states", C.c_void_p)]
 
@@ -162,6 +163,10 @@ def check(rc: int, what: str = ""):
 
 def _p(a):
     return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def _n(a):
+    return 0 if a is None else int(a.size)
 
 
 def _opts(level=None, max_width=None, tile_qubits=None, flags=0, op_cost=None, low_qubits=None):
@@ -225,7 +230,7 @@ class StateVector:
         m = None if mats is None else np.ascontiguousarray(mats, dtype=np.complex128)
         pr = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
         o = _opts(level, max_width, tile_qubits, flags)
-        check(_lib.qsim_apply(self.h, _p(g), len(g), _p(m), _p(pr), C.byref(o) if o else None),
+        check(_lib.qsim_apply(self.h, _p(g), len(g), _p(m), _n(m), _p(pr), _n(pr), C.byref(o) if o else None),
               "qsim_apply")
 
     def qsim_last_stats(self) -> dict:
@@ -238,9 +243,9 @@ class StateVector:
         check(_lib.qsim_measure(self.h, int(q), float(u), C.byref(o), C.byref(p)), "qsim_measure")
         return o.value, p.value
 
-    def qsim_measure_assert(self, q: int) -> float:
+    def qsim_measure_assert(self, q: int, want: int = 0) -> float:
         p = C.c_double()
-        check(_lib.qsim_measure_assert(self.h, int(q), C.byref(p)), "qsim_measure_assert")
+        check(_lib.qsim_measure_assert(self.h, int(q), int(want), C.byref(p)), "qsim_measure_assert")
         return p.value
 
     def qsim_reset(self, q: int):
@@ -271,7 +276,7 @@ class StateVector:
         pr = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
         best = qsim_fuse_opts()
         ns = C.c_double()
-        check(_lib.qsim_autotune(self.h, _p(g), len(g), _p(m), _p(pr), int(prefix_gates), C.byref(best),
+        check(_lib.qsim_autotune(self.h, _p(g), len(g), _p(m), _n(m), _p(pr), _n(pr), int(prefix_gates), C.byref(best),
                                  C.byref(ns)), "qsim_autotune")
         return best, ns.value
 
@@ -304,7 +309,7 @@ class Program:
         self.n = int(n)
         self.dtype = QSIM_DTYPES[dtype]
         p = C.c_void_p()
-        check(_lib.qsim_compile(self.n, self.dtype, _p(g), len(g), _p(m), _p(pr),
+        check(_lib.qsim_compile(self.n, self.dtype, _p(g), len(g), _p(m), _n(m), _p(pr), _n(pr),
                                 C.byref(o) if o else None, C.byref(p)), "qsim_compile")
         self.p = p
 
@@ -373,6 +378,7 @@ class Batch:
             a.g = g.ctypes.data
             a.ng = len(g)
             a.mats = None if mats is None else mats.ctypes.data
+            a.n_mats = 0 if mats is None else mats.size
             a.params = None if params is None else params.ctypes.data
             a.n_params = 0 if params is None else params.shape[1]
             a.uniforms = None if uni is None else uni.ctypes.data
@@ -549,11 +555,11 @@ def qsim_debug_fuse(n, gates, mats=None, params=None, level=5, max_width=4, flag
     out_m = np.zeros(min(cap_d, 2 * 1024 * 4096 + 2 * 16 * cap), dtype=np.float64)
     nops = C.c_size_t()
     counts = np.zeros(6, dtype=np.int64)
-    rc = _lib.qsim_debug_fuse(int(n), _p(g), len(g), _p(m), _p(pr), C.byref(o) if o else None,
+    rc = _lib.qsim_debug_fuse(int(n), _p(g), len(g), _p(m), _n(m), _p(pr), _n(pr), C.byref(o) if o else None,
                               _p(out_k), _p(out_q), _p(out_m), cap, len(out_m), C.byref(nops), _p(counts))
     if rc == E_CAPACITY:
         out_m = np.zeros(2 * 1024 * cap, dtype=np.float64)
-        rc = _lib.qsim_debug_fuse(int(n), _p(g), len(g), _p(m), _p(pr), C.byref(o) if o else None,
+        rc = _lib.qsim_debug_fuse(int(n), _p(g), len(g), _p(m), _n(m), _p(pr), _n(pr), C.byref(o) if o else None,
                                   _p(out_k), _p(out_q), _p(out_m), cap, len(out_m), C.byref(nops), _p(counts))
     check(rc, "qsim_debug_fuse")
     ops = []
@@ -598,7 +604,7 @@ def qsim_debug_emulate(n, gates, dtype="complex128", mats=None, params=None, lev
         out[0] = 1.0
     else:
         out = np.array(psi, dtype=np.complex128, copy=True)
-    check(_lib.qsim_debug_emulate(int(n), QSIM_DTYPES[dtype], _p(g), len(g), _p(m), _p(pr),
+    check(_lib.qsim_debug_emulate(int(n), QSIM_DTYPES[dtype], _p(g), len(g), _p(m), _n(m), _p(pr), _n(pr),
                                   C.byref(o) if o else None, _p(out)), "qsim_debug_emulate")
     return out
 
@@ -611,7 +617,7 @@ def qsim_debug_plan(n, gates, dtype="complex128", mats=None, params=None, level=
     pr = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
     o = _opts(level, max_width, tile_qubits, flags)
     s = qsim_apply_stats()
-    check(_lib.qsim_debug_plan(int(n), QSIM_DTYPES[dtype], _p(g), len(g), _p(m), _p(pr),
+    check(_lib.qsim_debug_plan(int(n), QSIM_DTYPES[dtype], _p(g), len(g), _p(m), _n(m), _p(pr), _n(pr),
                                C.byref(o) if o else None, C.byref(s)), "qsim_debug_plan")
     return s.as_dict()
 
@@ -623,3 +629,15 @@ def exported_symbols():
     txt = open(hdr).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b(qsim_[a-z0-9_]+)\s*\(", txt)))
+
+
+def qsim_stream_copy(dst, src, flags=0, rotate=0, stream=None):
+    """Device copy src -> dst (torch tensors of the same byte size; dst may be
+    src) with the tile kernel's grid shape; asynchronous on `stream` (default:
+    torch's current stream)."""
+    torch = _torch()
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes and src.is_cuda and dst.is_cuda
+    st = stream if stream is not None else torch.cuda.current_stream(src.device)
+    check(_lib.qsim_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes, int(flags),
+                                int(rotate) & 0xffffffff, C.c_void_p(st.cuda_stream)), "qsim_stream_copy")

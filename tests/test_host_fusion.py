@@ -145,6 +145,26 @@ def test_lowering_errors():
     assert e.value.code == qsim.E_UNSUPPORTED
 
 
+def test_parameter_and_matrix_bounds():
+    """A parameter slot past the caller's vector, or a MAT record whose
+    matrix runs past the caller's pool, is rejected (QSIM_E_ARG) instead of
+    reading beyond the arrays."""
+    g = W.gates([(W.KIND_RY, (0,), (0.0,), 3)])
+    ops, _ = qsim.qsim_debug_fuse(2, g, params=np.zeros(4))
+    assert len(ops) == 1
+    for params in (None, np.zeros(3)):
+        with pytest.raises(qsim.QsimError) as e:
+            qsim.qsim_debug_fuse(2, g, params=params)
+        assert e.value.code == qsim.E_ARG
+    m = W.gates([(W.KIND_MAT, (0, 1), ())])
+    m["mat_off"] = 4
+    ok = np.zeros(20, complex)
+    qsim.qsim_debug_fuse(2, m, mats=ok)
+    with pytest.raises(qsim.QsimError) as e:
+        qsim.qsim_debug_fuse(2, m, mats=np.zeros(19, complex))
+    assert e.value.code == qsim.E_ARG
+
+
 def test_plan_statistics():
     """The pass planner packs several fused operators per full-state pass."""
     g, _, _ = W.pauli_exponential_circuit(21, 1000, seed=2)

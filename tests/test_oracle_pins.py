@@ -193,6 +193,60 @@ def test_c3sqrtx_squares_to_c3x():
     np.testing.assert_allclose(a @ a, mat_of(W.KIND_C3X, 4), atol=1e-15)
 
 
+def test_sx_branch_is_h_s_h():
+    """SX is the square root of X with eigenvalues (1, i) on (|+>, |->): the
+    conjugation of S by H.  Squaring alone admits four roots of X; this fixes
+    the one the gate table names (and equals e^{i pi/4} exp(-i pi X / 4))."""
+    H, S = mat_of(W.KIND_H, 1), mat_of(W.KIND_S, 1)
+    SX = mat_of(W.KIND_SX, 1)
+    np.testing.assert_allclose(SX, H @ S @ H, atol=1e-15)
+    np.testing.assert_allclose(SX, np.exp(0.25j * math.pi) * scipy.linalg.expm(-0.25j * math.pi * PX),
+                               atol=1e-15)
+    plus = np.array([1, 1]) / math.sqrt(2)
+    minus = np.array([1, -1]) / math.sqrt(2)
+    np.testing.assert_allclose(SX @ plus, plus, atol=1e-15)
+    np.testing.assert_allclose(SX @ minus, 1j * minus, atol=1e-15)
+
+
+def test_c3sqrtx_is_controlled_sx_on_every_basis_state():
+    """C3XSQRTX applies SX (= H S H) to its last qubit when its three controls
+    are 1 and acts as the identity otherwise, on every basis state of 5
+    qubits and two qubit orders."""
+    n = 5
+    H, S = mat_of(W.KIND_H, 1), mat_of(W.KIND_S, 1)
+    sx = H @ S @ H
+    for qs in ((0, 2, 4, 1), (3, 1, 0, 4)):
+        for x in range(1 << n):
+            psi = np.zeros(1 << n, complex)
+            psi[x] = 1
+            got, _, _ = oracle.run(n, W.gates([(W.KIND_C3XSQRTX, qs, ())]), psi=psi)
+            want = psi.copy()
+            if all((x >> q) & 1 for q in qs[:3]):
+                want = full_operator(n, [qs[3]], sx) @ psi
+            np.testing.assert_allclose(got, want, atol=1e-15)
+
+
+def test_infidelity_checker():
+    """oracle.infidelity = 1 - |<a|b>|^2 / (<a|a><b|b>) on hand-computed
+    cases: orthogonal states give 1, a global phase or a rescaling gives 0,
+    and two overlaps worked out by hand give 1/2 and 3/4."""
+    rng = np.random.default_rng(5)
+    a = rng.normal(size=64) + 1j * rng.normal(size=64)
+    assert oracle.infidelity(a, a) < 1e-15
+    assert oracle.infidelity(a, np.exp(1.3j) * a) < 1e-15
+    assert oracle.infidelity(a, 7.5 * a) < 1e-15
+    e0 = np.zeros(8, complex); e0[0] = 1
+    e5 = np.zeros(8, complex); e5[5] = 1
+    assert oracle.infidelity(e0, e5) == 1.0
+    assert oracle.infidelity(a[:8], a[:8] - np.vdot(e0, a[:8]) * e0) == pytest.approx(
+        abs(a[0]) ** 2 / np.vdot(a[:8], a[:8]).real, rel=1e-12)
+    # <a|b> = 1/sqrt(2) for a = |0>, b = (|0> + |1>)/sqrt(2), also unnormalised
+    assert oracle.infidelity([1, 0], [1, 1]) == pytest.approx(0.5, abs=1e-16)
+    # a = (|0> + i|1>)/sqrt(2), b = (|0> + |2>)/sqrt(2): <a|b> = 1/2
+    assert oracle.infidelity(np.array([1, 1j, 0]) / math.sqrt(2),
+                             np.array([1, 0, 1]) / math.sqrt(2)) == pytest.approx(0.75, abs=1e-15)
+
+
 # -------------------------------------------------- whole circuits
 def test_random_circuits_match_brute_force():
     """Every fixed gate kind in random circuits on n <= 7 against explicit

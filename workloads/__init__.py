@@ -459,3 +459,14 @@ def inverse_circuit(g: np.ndarray) -> np.ndarray:
         elif k not in self_inverse:
             raise ValueError(f"no inverse record for kind {k}")
     return out
+
+
+def probe_vectors(n: int, count: int, seed: int = 4049):
+    """Yield ``count`` complex vectors of length 2^n with independent N(0,1)
+    real and imaginary parts (E|r_x|^2 = 2).  For any fixed d, |<r|d>|^2
+    averaged over such vectors estimates 2 ||d||^2: the tests compare a
+    state with a stored one through these overlaps when the stored state is
+    too large to keep."""
+    for k in range(count):
+        rng = _rng(seed, 97, k)
+        yield rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
