@@ -201,6 +201,21 @@ int qsim_expval(qsim_h h, const qsim_pauli *t, size_t nt, double *out);
  * Synchronous. */
 int qsim_probs(qsim_h h, const int *qs, int nqs, double *out);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): qsim_probs without any
+ * allocation and without host synchronisation.  Same inputs and checks as
+ * qsim_probs; the 2^nqs probabilities go to `dev_out`, caller-owned device
+ * memory, asynchronously on the handle's stream (read them after that stream
+ * is synchronised).  The reduction partials live in a fixed device array of
+ * 2^17 + 4096 doubles (about 1 MiB), one per GPU, held until the process
+ * ends; up to 8 qubits the reduction order, and so every bit of the result,
+ * equals qsim_probs, and above 8 the state is cut into fewer chunks.  All
+ * calls on one GPU share that array: calls that overlap on a GPU (other
+ * streams, other threads) race and must be serialised by the caller.  The
+ * zero vector gives NaN entries (0/0) instead of QSIM_E_ZERO_PROB.  Errors:
+ * QSIM_E_ARG, QSIM_E_QUBIT, QSIM_E_HIP. */
+int qsim_probs_noalloc(qsim_h h, const int *qs, int nqs, double *dev_out);
+
 /* <psi|psi> in FP64: the squared norm that renormalisation after a
  * projective measurement divides by (Section 4.3); for complex64 states it
  * also shows the rounding drift of the sweeps.  Synchronous. */

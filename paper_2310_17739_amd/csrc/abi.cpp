@@ -732,6 +732,18 @@ int qsim_reset(qsim_h h, int q) {
     return qk::launch_sweep(h->dtype, h->buf, 0, 1, h->n, x, h->d_small, h->stream);
 }
 
+int qsim_probs_noalloc(qsim_h h, const int *qs, int nqs, double *dev_out) {
+    if (!h || !dev_out || nqs < 0 || nqs > 12 || (nqs && !qs)) return QSIM_E_ARG;
+    int local[12];
+    for (int i = 0; i < nqs; i++) {
+        if (qs[i] < 0 || qs[i] >= h->n) return QSIM_E_QUBIT;
+        for (int j = 0; j < i; j++)
+            if (qs[j] == qs[i]) return QSIM_E_QUBIT;
+        local[i] = qs[i];
+    }
+    return qk::launch_probs_noalloc(h->dtype, h->buf, h->n, local, nqs, dev_out, h->stream);
+}
+
 int qsim_norm(qsim_h h, double *out) {
     if (!h || !out) return QSIM_E_ARG;
     int rc = marginal(h, nullptr, 0);

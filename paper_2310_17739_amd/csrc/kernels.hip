@@ -23,6 +23,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "launch.h"
 #include "swizzle.h"
@@ -1249,6 +1250,59 @@ int launch_marginal(int dtype, const void *state, uint64_t sstride, uint32_t nst
     else
         hipLaunchKernelGGL(k_marginal<double>, grid, dim3(NT), 0, st, (const Cx<double> *)state, sstride, a, partials);
     hipLaunchKernelGGL(k_finish, dim3(uint32_t(nstates) << nqs), dim3(NT), 0, st, partials, nchunks, out);
+    return check(hipGetLastError());
+}
+
+// ------------------------------------------- allocation-free marginals
+// Reduction scratch of launch_probs_noalloc: a fixed device array, one copy
+// per GPU, that lives until the process ends.  Host code never uses its name
+// as an address: the device address comes from hipGetSymbolAddress, once per
+// device, and only that pointer reaches the kernels.
+constexpr uint32_t kScratchPartials = 1u << 17;            // doubles of chunk partials
+constexpr uint32_t kScratchDoubles = kScratchPartials + 4096;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+// out[j] = raw[j] / sum_j raw[j], the sum taken in index order by one thread
+// (the order a host loop over the same values uses).
+__global__ void __launch_bounds__(NT) k_normalize(const double *__restrict__ raw, uint32_t m,
+                                                  double *__restrict__ out) {
+    __shared__ double tot;
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (uint32_t j = 0; j < m; j++) s += raw[j];
+        tot = s;
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < m; j += NT) out[j] = raw[j] / tot;
+}
+
+int launch_probs_noalloc(int dtype, const void *state, int n, const int *qs, int nqs, double *dev_out,
+                         hipStream_t st) {
+    if (nqs < 0 || nqs > 12 || nqs > n) return QSIM_E_ARG;
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *ptrs[kMaxDevices] = {};
+    int dev = 0;
+    int rc = note_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (rc) return rc;
+    if (dev < 0 || dev >= kMaxDevices) return QSIM_E_ARG;
+    double *base;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!ptrs[dev]) {
+            void *p = nullptr;
+            rc = note_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+            if (rc) return rc;
+            ptrs[dev] = static_cast<double *>(p);
+        }
+        base = ptrs[dev];
+    }
+    double *partials = base, *raw = base + kScratchPartials;
+    const uint32_t cap = kScratchPartials >> nqs;
+    const uint32_t nch = marginal_chunks(n, nqs) < cap ? marginal_chunks(n, nqs) : cap;
+    rc = launch_marginal(dtype, state, 0, 1, n, qs, nqs, partials, raw, st, nch);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_normalize, dim3(1), dim3(NT), 0, st, raw, 1u << nqs, dev_out);
     return check(hipGetLastError());
 }
 

@@ -119,6 +119,15 @@ int launch_marginal(int dtype, const void *state, uint64_t sstride, uint32_t nst
                     uint32_t nchunks = 0);
 uint32_t marginal_chunks(int n, int nqs);
 
+// The marginal of qubits qs[0..nqs-1] normalised by its total, written to
+// device memory dev_out (2^nqs doubles), with the reduction partials in a
+// fixed per-device scratch array instead of an allocated buffer (at most
+// 2^17 partials: for nqs > 8 the state is cut into fewer chunks than
+// launch_marginal would use).  Calls that overlap on one device race on the
+// scratch.
+int launch_probs_noalloc(int dtype, const void *state, int n, const int *qs, int nqs, double *dev_out,
+                         hipStream_t st);
+
 // Pauli-term overlaps S_k = sum_x (-1)^{popcount(x & z_k)} conj(a[x ^ x_k]) a[x]
 // (complex, FP64) for terms on device (masks arrays), written as
 // out[(b * nterms + k) * 2 + {0,1}].

@@ -83,6 +83,7 @@ def _load():
         "qsim_expval": ([P, P, SZ, P], I),
         "qsim_probs": ([P, P, I, P], I),
         "qsim_norm": ([P, P], I),
+        "qsim_probs_noalloc": ([P, P, I, P], I),
         "qsim_get_state": ([P, P], I),
         "qsim_set_state": ([P, P], I),
         "qsim_debug_fuse": ([I, P, SZ, P, SZ, P, SZ, P, P, P, P, SZ, SZ, P, P], I),
@@ -262,6 +263,14 @@ class StateVector:
         out = np.zeros(1 << len(q), dtype=np.float64)
         check(_lib.qsim_probs(self.h, _p(q), len(q), _p(out)), "qsim_probs")
         return out
+
+    def qsim_probs_noalloc(self, qs, dev_out):
+        """qsim_probs into a caller-owned float64 device tensor `dev_out`
+        (2^len(qs) entries), asynchronously on the state's stream."""
+        q = np.ascontiguousarray(qs, dtype=np.int32)
+        assert dev_out.is_cuda and dev_out.numel() >= (1 << len(q)) and dev_out.element_size() == 8
+        check(_lib.qsim_probs_noalloc(self.h, _p(q), len(q), C.c_void_p(dev_out.data_ptr())),
+              "qsim_probs_noalloc")
 
     def qsim_norm(self) -> float:
         out = C.c_double()
