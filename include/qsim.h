@@ -120,9 +120,14 @@ typedef struct qsim_fuse_opts {
 enum {
     QSIM_F_ONE_OP_PER_PASS = 1,  /* every fused operator is its own full-state sweep */
     QSIM_F_NO_SPARSE = 2,        /* treat fused operators as dense (no zero skipping) */
-    QSIM_F_FULL_SUPPORT = 4      /* keep every qubit of an operator in its LDS tile
+    QSIM_F_FULL_SUPPORT = 4,     /* keep every qubit of an operator in its LDS tile
                                     (default: qubits on which the operator is
                                     diagonal may stay outside the tile) */
+    QSIM_F_REG_ENGINE = 8        /* tiled passes of 10..13 qubits keep the tile in
+                                    registers: operators run on a thread's register
+                                    bits, qubits reach those bits through lane
+                                    exchanges (v_permlane16/32_swap) or LDS
+                                    re-layouts (also: QSIM_REG_ENGINE=1) */
 };
 
 /* Counters of the last qsim_apply (host-side compile and device plan). */
@@ -136,6 +141,9 @@ typedef struct qsim_apply_stats {
     double compile_seconds;   /* host time spent lowering, fusing, planning, packing */
     int32_t tile_qubits;      /* tile size used */
     int32_t max_width;        /* fusion width used */
+    int64_t reg_passes;       /* passes whose tile stays in registers */
+    int64_t reg_swaps;        /* lane/register exchanges in those passes */
+    int64_t reg_relayouts;    /* LDS re-layouts in those passes */
 } qsim_apply_stats;
 
 /* ------------------------------------------------------------------ core */

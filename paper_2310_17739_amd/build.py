@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqsim.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HOST_SOURCES = ["gates.cpp", "fuse.cpp", "plan.cpp", "qasm.cpp", "abi.cpp", "batch.cpp", "serve.cpp"]
+HOST_SOURCES = ["gates.cpp", "fuse.cpp", "plan.cpp", "regplan.cpp", "qasm.cpp", "abi.cpp", "batch.cpp", "serve.cpp"]
 DEVICE_SOURCES = ["kernels.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

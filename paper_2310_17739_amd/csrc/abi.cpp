@@ -61,6 +61,8 @@ void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc
     // 16 outputs then fit the registers without chunking
     pc->threads = env_int("QSIM_TILE_THREADS", dtype == QSIM_C64 ? 512 : 256) == 256 ? 256 : 512;
     pc->first_in_regs = env_int("QSIM_FIRST_IN_REGS", 1) != 0;
+    pc->reg_engine = env_int("QSIM_REG_ENGINE", 0) != 0;
+    pc->reg_coalesce = env_int("QSIM_REG_COALESCE", 1) != 0;
     if (opt) {
         if (opt->level >= 0 && opt->level <= 5) fc->level = opt->level;
         if (opt->max_width > 0) fc->max_width = opt->max_width;
@@ -69,6 +71,7 @@ void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc
         pc->one_op_per_pass = (opt->flags & QSIM_F_ONE_OP_PER_PASS) != 0;
         fc->sparse = (opt->flags & QSIM_F_NO_SPARSE) == 0;
         pc->full_support = (opt->flags & QSIM_F_FULL_SUPPORT) != 0;
+        if (opt->flags & QSIM_F_REG_ENGINE) pc->reg_engine = true;
     }
     if (dtype == QSIM_C128) fc->max_width = std::min(fc->max_width, 4);
     fc->max_width = std::max(1, std::min(fc->max_width, kMaxK));
@@ -89,6 +92,78 @@ void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc
     pc->meta_budget = std::min(room, size_t(std::max(1024, env_int("QSIM_META_BUDGET", 16 * 1024))));
 }
 
+// A register-resident pass: tile qubits partition the n qubits, layouts are
+// permutations of the tile positions, every record is well formed, the
+// re-layout records name the layout the swaps and re-layouts before them
+// leave (so the kernel's LDS writes are a permutation of the tile), and
+// coefficient ranges lie inside the pass's share of the table.
+int validate_reg_pass(int n, int dtype, const Compiled &c, size_t i) {
+    const PackedPlan &p = c.plan;
+    const PassInfo &pi = c.passes[i];
+    const qk::RegArgs &ra = pi.ra;
+    const int t = ra.t;
+    const uint64_t all = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
+    if (pi.strided || pi.kind != Pass::TILE || ra.n != n || reg_threads_for(t) == 0 || t >= n || n - t > 31)
+        return QSIM_E_ARG;
+    const uint32_t nrec = p.pass_begin[i + 1] - p.pass_begin[i];
+    bool any_xpose = false;
+    for (uint32_t j = p.pass_begin[i]; j < p.pass_begin[i + 1] && j < p.ops.size(); j++)
+        any_xpose |= p.ops[j].kind == DEVOP_XPOSE;
+    if (size_t(ra.lds_bytes) != qk::reg_lds_bytes(elem_bytes(dtype), t, any_xpose, nrec) ||
+        ra.lds_bytes > qk::max_lds_bytes())
+        return QSIM_E_ARG;
+    if (ra.flags & ~uint32_t(qk::RF_NONTEMPORAL)) return QSIM_E_ARG;
+    uint64_t tile = 0;
+    for (int j = 0; j < t; j++) {
+        if (ra.tq[j] >= n || (j && ra.tq[j] <= ra.tq[j - 1])) return QSIM_E_ARG;
+        tile |= uint64_t(1) << ra.tq[j];
+    }
+    if ((tile & ra.rest_mask) || ((tile | ra.rest_mask) != all)) return QSIM_E_ARG;
+    auto is_perm = [&](const uint8_t *pos) {
+        uint32_t seen = 0;
+        for (int x = 0; x < t; x++) {
+            if (pos[x] >= t || ((seen >> pos[x]) & 1)) return false;
+            seen |= 1u << pos[x];
+        }
+        return true;
+    };
+    if (!is_perm(ra.load_pos) || !is_perm(ra.store_pos)) return QSIM_E_ARG;
+    const uint32_t rb = p.pass_begin[i], re = p.pass_begin[i + 1];
+    if (rb > re || re > p.ops.size() || p.coef_begin[i] > p.coef_begin[i + 1] ||
+        p.coef_begin[i + 1] > p.coefs.size())
+        return QSIM_E_ARG;
+    const int logt = t - kRegBits;
+    uint8_t cur[16];
+    std::memcpy(cur, ra.load_pos, 16);
+    for (uint32_t j = rb; j < re; j++) {
+        const DevOp &o = p.ops[j];
+        if (o.kind == DEVOP_RMAT) {
+            if (o.k != kRegBits || o.kx > kMaxK || !o.present || (o.present >> (1 << kRegBits))) return QSIM_E_ARG;
+            for (int a = 0; a < o.kx; a++) {
+                if (o.xq[a] >= n || ((tile >> o.xq[a]) & 1)) return QSIM_E_ARG;
+                if (a && o.xq[a] <= o.xq[a - 1]) return QSIM_E_ARG;
+            }
+            if (p.op_np[j] < 0 || p.op_np[j] > 3) return QSIM_E_ARG;
+            const size_t need = size_t(o.coef) + size_t(devop_coefs(o)) * (size_t(1) << p.op_np[j]);
+            if (o.coef < p.coef_begin[i] || need > p.coef_begin[i + 1]) return QSIM_E_ARG;
+        } else if (o.kind == DEVOP_SWAP) {
+            if ((o.pos[0] != 4 && o.pos[0] != 5) || o.pos[1] >= kRegBits) return QSIM_E_ARG;
+            std::swap(cur[o.pos[0]], cur[logt + o.pos[1]]);
+        } else if (o.kind == DEVOP_XPOSE) {
+            if (j + 1 >= re || p.ops[j + 1].kind != DEVOP_XPOSE2) return QSIM_E_ARG;
+            const uint8_t *from = reinterpret_cast<const uint8_t *>(&o);
+            const uint8_t *to = reinterpret_cast<const uint8_t *>(&p.ops[j + 1]);
+            if (!is_perm(from) || !is_perm(to) || std::memcmp(from, cur, size_t(t)) != 0) return QSIM_E_ARG;
+            std::memcpy(cur, to, size_t(t));
+            j++;
+        } else {
+            return QSIM_E_ARG;
+        }
+    }
+    if (std::memcmp(cur, ra.store_pos, size_t(t)) != 0) return QSIM_E_ARG;
+    return QSIM_OK;
+}
+
 // Check, before anything is launched, that every device record stays inside
 // the buffers and tiles the kernels will index: tile qubits partition the n
 // qubits, operator positions are ascending and inside the tile (or the
@@ -101,6 +176,11 @@ int validate_plan(int n, int dtype, const Compiled &c) {
     for (size_t i = 0; i < c.passes.size(); i++) {
         const PassInfo &pi = c.passes[i];
         int width = n;
+        if (pi.reg) {
+            const int rc = validate_reg_pass(n, dtype, c, i);
+            if (rc) return rc;
+            continue;
+        }
         if (pi.kind == Pass::MEASURE) {
             if (p.pass_begin[i] != p.pass_begin[i + 1] || pi.meas.q < 0 || pi.meas.q >= n) return QSIM_E_ARG;
             continue;
@@ -218,8 +298,13 @@ int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const GateI
         need[i] = pc.full_support ? L.ops[i].mask() : op_moved_qubits(L.ops[i], present[i]);
     std::vector<Pass> passes;
     plan_passes(n, L, meta, need, pc, &passes);
+    // tiled passes of 10..13 qubits (not whole-state ones, which may hold
+    // measurement records) run register-resident
+    for (Pass &p : passes)
+        p.reg = pc.reg_engine && p.kind == Pass::TILE && !p.strided && p.t < n && reg_threads_for(p.t) > 0 &&
+                p.c <= 4 && p.inline_meas.empty();
     place_positions(n, L.ops, pc.threads == 512 ? 9 : 8, first_regs_max_k(dtype), pc.first_in_regs, &passes);
-    rc = pack_plan(L.ops, present, passes, &out->plan);
+    rc = pack_plan(L.ops, present, passes, pc, &out->plan);
     if (rc) return rc;
     // LDS slot offsets of the tile positions (the tile kernel's layout)
     for (size_t i = 0; i < passes.size(); i++) {
@@ -248,6 +333,25 @@ int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const GateI
         pi.ta.regs = (p.first_in_regs ? 1 : 0) | (p.last_in_regs ? 2 : 0) | (p.last_off << 2);
         for (int h = 0; h < p.nhi; h++) pi.ta.hi[h] = uint8_t(p.hi[h]);
         for (int j = 0; j < 16; j++) pi.ta.tq[j] = p.tq[j];
+        if (p.reg) {
+            pi.reg = true;
+            pi.ra.rest_mask = pi.ta.rest_mask;
+            pi.ra.n = n;
+            pi.ra.t = p.t;
+            pi.ra.lds_bytes = uint32_t(qk::reg_lds_bytes(elem_bytes(dtype), p.t, p.reg_xposes > 0,
+                                                         out->plan.pass_begin[out->passes.size() + 1] -
+                                                             out->plan.pass_begin[out->passes.size()]));
+            // states beyond the 256 MB Infinity Cache stream from HBM:
+            // non-temporal loads and stores there
+            pi.ra.flags = ((elem_bytes(dtype) << n) > (size_t(256) << 20)) ? qk::RF_NONTEMPORAL : 0u;
+            for (int j = 0; j < 16; j++) {
+                pi.ra.tq[j] = p.tq[j];
+                pi.ra.load_pos[j] = p.load_pos[j];
+                pi.ra.store_pos[j] = p.store_pos[j];
+            }
+            out->stats_reg_swaps += p.reg_swaps;
+            out->stats_reg_xposes += p.reg_xposes;
+        }
         out->passes.push_back(pi);
     }
     qsim_apply_stats &s = out->stats;
@@ -260,6 +364,9 @@ int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const GateI
     s.bytes_moved = int64_t(passes.size()) * 2 * (int64_t(1) << n) * int64_t(elem_bytes(dtype));
     s.tile_qubits = pc.one_op_per_pass ? 0 : pc.tile_qubits;
     s.max_width = fc.max_width;
+    for (const PassInfo &pi : out->passes) s.reg_passes += pi.reg ? 1 : 0;
+    s.reg_swaps = out->stats_reg_swaps;
+    s.reg_relayouts = out->stats_reg_xposes;
     s.compile_seconds = now_seconds() - t0;
     // parameterised templates are validated after their coefficient layout
     // is bound (qsim_batch_create)
@@ -368,6 +475,11 @@ int enqueue_passes(const Compiled &c, const DeviceTables &dt, int dtype, void *s
                 rc = qk::launch_sweep(dtype, state, 0, 1, pi.ta.n, p.ops[j], dt.d_coefs, st);
                 if (rc) return rc;
             }
+        } else if (pi.reg) {
+            uint32_t flags = (init_zero_first && i == 0) ? qk::TF_INIT_ZERO : 0u;
+            rc = qk::launch_reg(dtype, state, 0, 1, pi.ra, dt.d_ops, ob, oe, dt.d_coefs, p.coef_begin[i],
+                                p.coef_begin[i + 1], 0, nullptr, flags, st);
+            if (rc) return rc;
         } else {
             uint32_t flags = (init_zero_first && i == 0) ? qk::TF_INIT_ZERO : 0u;
             rc = qk::launch_tile(dtype, state, 0, 1, pi.ta, dt.d_ops, ob, oe, dt.d_coefs,
@@ -634,6 +746,9 @@ int qsim_run_timed(qsim_h h, qsim_prog p) {
             rc = QSIM_OK;
             for (uint32_t j = pl.pass_begin[i]; j < pl.pass_begin[i + 1] && !rc; j++)
                 rc = qk::launch_sweep(p->dtype, h->buf, 0, 1, p->n, pl.ops[j], p->dt.d_coefs, h->stream);
+        } else if (pi.reg) {
+            rc = qk::launch_reg(p->dtype, h->buf, 0, 1, pi.ra, p->dt.d_ops, pl.pass_begin[i], pl.pass_begin[i + 1],
+                                p->dt.d_coefs, pl.coef_begin[i], pl.coef_begin[i + 1], 0, nullptr, 0, h->stream);
         } else {
             rc = qk::launch_tile(p->dtype, h->buf, 0, 1, pi.ta, p->dt.d_ops, pl.pass_begin[i],
                                  pl.pass_begin[i + 1], p->dt.d_coefs, pl.coef_begin[i],
@@ -1031,6 +1146,80 @@ int qsim_debug_emulate(int n, int dtype, const qsim_gate *g, size_t ng, const do
                 const DevOp &o = p.ops[j];
                 if (o.kind != DEVOP_MAT || o.kx) return QSIM_E_ARG;
                 apply(st, n, o, p.coefs.data() + o.coef);
+            }
+            continue;
+        }
+        if (pi.reg) {
+            // register-resident pass: elements indexed by position bits
+            // (thread bits, then register bits), moved as the kernel moves them
+            const qk::RegArgs &ra = pi.ra;
+            const int t = ra.t, logt = t - kRegBits;
+            std::vector<cd> v(size_t(1) << t), w(v.size());
+            for (uint64_t tile = 0; tile < (uint64_t(1) << (n - t)); tile++) {
+                uint64_t base = 0, bits = tile;
+                for (int q = 0; q < n; q++)
+                    if ((ra.rest_mask >> q) & 1) {
+                        if (bits & 1) base |= uint64_t(1) << q;
+                        bits >>= 1;
+                    }
+                auto addr = [&](uint64_t P, const uint8_t *pos) {
+                    uint64_t a = base;
+                    for (int b = 0; b < t; b++)
+                        if ((P >> b) & 1) a |= uint64_t(1) << ra.tq[pos[b]];
+                    return a;
+                };
+                uint8_t cur[16];
+                std::memcpy(cur, ra.load_pos, 16);
+                for (uint64_t P = 0; P < v.size(); P++) v[P] = st[addr(P, ra.load_pos)];
+                for (uint32_t j = p.pass_begin[i]; j < p.pass_begin[i + 1]; j++) {
+                    const DevOp &o = p.ops[j];
+                    if (o.kind == DEVOP_RMAT) {
+                        uint32_t e = 0;
+                        for (int x = 0; x < o.kx; x++) e |= uint32_t((base >> o.xq[x]) & 1) << x;
+                        const cd *cf = p.coefs.data() + o.coef + (size_t(e) * __builtin_popcount(o.present) << 4);
+                        for (uint64_t tid = 0; tid < (uint64_t(1) << logt); tid++) {
+                            cd x[16], y[16];
+                            for (int r = 0; r < 16; r++) x[r] = v[tid | (uint64_t(r) << logt)];
+                            for (int r = 0; r < 16; r++) {
+                                cd acc = 0;
+                                int term = 0;
+                                for (int M = 0; M < 16; M++)
+                                    if ((o.present >> M) & 1) acc += cf[size_t(term++) * 16 + r] * x[r ^ M];
+                                y[r] = acc;
+                            }
+                            for (int r = 0; r < 16; r++) v[tid | (uint64_t(r) << logt)] = y[r];
+                        }
+                    } else if (o.kind == DEVOP_SWAP) {
+                        const int a = o.pos[0], b = logt + o.pos[1];
+                        for (uint64_t P = 0; P < v.size(); P++) {
+                            const uint64_t ba = (P >> a) & 1, bb = (P >> b) & 1;
+                            uint64_t Q = P & ~((uint64_t(1) << a) | (uint64_t(1) << b));
+                            Q |= (ba << b) | (bb << a);
+                            w[Q] = v[P];
+                        }
+                        std::swap(v, w);
+                        std::swap(cur[a], cur[b]);
+                    } else if (o.kind == DEVOP_XPOSE && j + 1 < p.pass_begin[i + 1]) {
+                        const uint8_t *from = reinterpret_cast<const uint8_t *>(&o);
+                        const uint8_t *to = reinterpret_cast<const uint8_t *>(&p.ops[j + 1]);
+                        if (std::memcmp(from, cur, size_t(t)) != 0) return QSIM_E_ARG;
+                        int to_pos[16];
+                        for (int b = 0; b < t; b++) to_pos[to[b]] = b;
+                        for (uint64_t P = 0; P < v.size(); P++) {
+                            uint64_t Q = 0;
+                            for (int b = 0; b < t; b++)
+                                if ((P >> b) & 1) Q |= uint64_t(1) << to_pos[from[b]];
+                            w[Q] = v[P];
+                        }
+                        std::swap(v, w);
+                        std::memcpy(cur, to, size_t(t));
+                        j++;
+                    } else {
+                        return QSIM_E_ARG;
+                    }
+                }
+                if (std::memcmp(cur, ra.store_pos, size_t(t)) != 0) return QSIM_E_ARG;
+                for (uint64_t P = 0; P < v.size(); P++) st[addr(P, ra.store_pos)] = v[P];
             }
             continue;
         }

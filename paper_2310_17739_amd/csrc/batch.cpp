@@ -118,7 +118,7 @@ size_t bind_layout(Compiled *c, std::vector<qk::BindEntry> *ents, uint32_t *max_
     *max_count = 0;
     for (size_t j = 0; j < p.ops.size(); j++) {
         DevOp &o = p.ops[j];
-        if (o.kind != DEVOP_MAT) continue;
+        if (!devop_is_mat(o.kind)) continue;
         const uint32_t count = devop_coefs(o);
         qk::BindEntry e{};
         e.bound_off = uint32_t(bound);
@@ -137,7 +137,7 @@ size_t bind_layout(Compiled *c, std::vector<qk::BindEntry> *ents, uint32_t *max_
     for (size_t i = 0; i + 1 < p.pass_begin.size(); i++) {
         new_begin[i] = uint32_t(run);
         for (uint32_t j = p.pass_begin[i]; j < p.pass_begin[i + 1]; j++)
-            if (p.ops[j].kind == DEVOP_MAT) run += devop_coefs(p.ops[j]);
+            if (devop_is_mat(p.ops[j].kind)) run += devop_coefs(p.ops[j]);
     }
     new_begin.back() = uint32_t(run);
     p.coef_begin = new_begin;
@@ -296,6 +296,11 @@ int enqueue_group(const Group &G, int dtype, hipStream_t st) {
             for (uint32_t j = p.pass_begin[i]; j < p.pass_begin[i + 1] && !rc; j++)
                 rc = qk::launch_sweep(dtype, G.d_states, G.sstride, uint32_t(G.nstates), G.n, p.ops[j],
                                       G.d_coefs, st, G.cstride, G.d_status);
+        } else if (pi.reg) {
+            const uint32_t flags = (i == 0 && first_tile) ? qk::TF_INIT_ZERO : 0u;
+            rc = qk::launch_reg(dtype, G.d_states, G.sstride, uint32_t(G.nstates), pi.ra, G.d_ops,
+                                p.pass_begin[i], p.pass_begin[i + 1], G.d_coefs, p.coef_begin[i],
+                                p.coef_begin[i + 1], G.cstride, G.d_status, flags, st);
         } else {
             const uint32_t flags = (i == 0 && first_tile) ? qk::TF_INIT_ZERO : 0u;
             rc = qk::launch_tile(dtype, G.d_states, G.sstride, uint32_t(G.nstates), pi.ta, G.d_ops,

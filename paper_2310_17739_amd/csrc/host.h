@@ -119,6 +119,16 @@ struct Pass {
     bool first_in_regs = false;   // the first operator runs on the loaded registers
     bool last_in_regs = false;    // the last operator runs on the registers stored
     int last_off = 0;             // its first register-index bit
+    // register-resident passes (see pack_reg_pass): the tile lives in the
+    // threads' registers; position p of an element index (lane bits 0..5,
+    // wave bits 6..logt-1, register bits logt..t-1) holds canonical tile
+    // bit load_pos[p] as loaded and store_pos[p] as stored (canonical bit c
+    // is the c-th smallest tile qubit)
+    bool reg = false;
+    int reg_logt = 0;
+    uint8_t load_pos[16] = {0};
+    uint8_t store_pos[16] = {0};
+    int reg_swaps = 0, reg_xposes = 0;
 };
 
 struct PlanConfig {
@@ -131,7 +141,14 @@ struct PlanConfig {
     bool one_op_per_pass = false;
     bool full_support = false;    // every qubit of an operator in its tile
     bool first_in_regs = true;    // apply a pass's first operator before the tile reaches LDS
+    bool reg_engine = false;      // tiled passes of 10..13 qubits run register-resident
+    bool reg_coalesce = true;     // restore the low qubits to lane bits 0..c-1 before the store
 };
+
+// Register bits of a register-resident pass: each thread holds 2^kRegBits
+// amplitudes, so a tile of t qubits takes 2^(t - kRegBits) threads.
+constexpr int kRegBits = 4;
+inline int reg_threads_for(int t) { return (t >= 10 && t <= 13) ? (1 << (t - kRegBits)) : 0; }
 
 // meta_bytes[i]: LDS bytes operator i needs in a tiled pass (record +
 // coefficients at the state precision); need[i]: the qubits operator i must
@@ -179,7 +196,15 @@ static_assert(sizeof(DevOp) == 32, "DevOp layout");
 // shift's 2^k diagonal entries.
 inline uint32_t devop_coefs(const DevOp &o) { return uint32_t(__builtin_popcount(o.present)) << (o.k + o.kx); }
 
-enum { DEVOP_MAT = 0, DEVOP_MEASURE = 1, DEVOP_ASSERT0 = 2, DEVOP_RESET = 3 };
+enum { DEVOP_MAT = 0, DEVOP_MEASURE = 1, DEVOP_ASSERT0 = 2, DEVOP_RESET = 3,
+       // register-resident passes:
+       DEVOP_RMAT = 4,    // operator on the kRegBits register bits: present = register XOR
+                          // shifts, k = kRegBits, coefficients 2^k per shift, kx / xq block qubits
+       DEVOP_SWAP = 5,    // pos[0] = lane bit (4 or 5), pos[1] = register bit: exchange them
+       DEVOP_XPOSE = 6,   // LDS re-layout; bytes 0..13 = canonical bit per position before,
+       DEVOP_XPOSE2 = 7   // and, in the record that follows, after
+};
+inline bool devop_is_mat(int kind) { return kind == DEVOP_MAT || kind == DEVOP_RMAT; }
 
 struct PackedPlan {
     std::vector<DevOp> ops;             // in pass order
@@ -204,7 +229,17 @@ uint64_t op_moved_qubits(const Op &o, uint32_t present);
 // layout holds the 2^np basis blocks (a bind step combines them).  Returns
 // QSIM_OK, or QSIM_E_ARG if a tiled pass leaves a moved qubit outside its tile.
 int pack_plan(const std::vector<Op> &ops, const std::vector<uint32_t> &present,
-              const std::vector<Pass> &passes, PackedPlan *out);
+              std::vector<Pass> &passes, const PlanConfig &cfg, PackedPlan *out);
+
+// Register program of one tiled pass (regplan.cpp): appends the pass's
+// records and coefficients to `out` and sets p.load_pos / p.store_pos.
+// Every operator runs on the register bits: before it, qubits it needs that
+// sit on lane bits 4 or 5 are swapped in (DEVOP_SWAP), others are brought in
+// by an LDS re-layout (DEVOP_XPOSE pair), which also chooses the qubits the
+// next operators need (furthest next use leaves first).  Returns QSIM_OK or
+// QSIM_E_ARG for an operator the pass cannot hold.
+int pack_reg_pass(const std::vector<Op> &ops, const std::vector<uint32_t> &present, Pass &p,
+                  bool coalesce, PackedPlan *out);
 
 double now_seconds();
 

@@ -730,6 +730,253 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
     }
 }
 
+// ------------------------------------------------ register-resident pass
+// Thread `tid` of a 2^LOGT-thread workgroup holds 16 amplitudes of the tile
+// in v[0..15]; element (tid, i) sits at position bits tid (lane bits 0..5,
+// wave bits 6..LOGT-1) and i (register bits LOGT..LOGT+3).  A layout names
+// the canonical tile bit each position carries (see the host planner).
+
+// Exchange lane bit 5 (LANE5) or 4 with register bit RB: registers i and
+// i | 2^RB trade the half of their lanes whose lane bit differs from the
+// register bit (v_permlane32_swap / v_permlane16_swap on every 32-bit word).
+template <typename T, int RB, bool LANE5>
+__device__ __forceinline__ void reg_swap(Cx<T> (&v)[16]) {
+    constexpr int W = int(sizeof(Cx<T>) / 4);
+    static_for<0, 16>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if constexpr (!((i >> RB) & 1)) {
+            constexpr int j = i | (1 << RB);
+            uint32_t a[W], b[W];
+            __builtin_memcpy(a, &v[i], sizeof(a));
+            __builtin_memcpy(b, &v[j], sizeof(b));
+#pragma unroll
+            for (int d = 0; d < W; d++) {
+                if constexpr (LANE5) {
+                    const auto r = __builtin_amdgcn_permlane32_swap(a[d], b[d], false, false);
+                    a[d] = r[0];
+                    b[d] = r[1];
+                } else {
+                    const auto r = __builtin_amdgcn_permlane16_swap(a[d], b[d], false, false);
+                    a[d] = r[0];
+                    b[d] = r[1];
+                }
+            }
+            __builtin_memcpy(&v[i], a, sizeof(a));
+            __builtin_memcpy(&v[j], b, sizeof(b));
+        }
+    });
+}
+
+template <typename T, bool LANE5>
+__device__ __forceinline__ void reg_swap_rb(Cx<T> (&v)[16], int rb) {
+    switch (rb) {
+    case 0: reg_swap<T, 0, LANE5>(v); break;
+    case 1: reg_swap<T, 1, LANE5>(v); break;
+    case 2: reg_swap<T, 2, LANE5>(v); break;
+    default: reg_swap<T, 3, LANE5>(v); break;
+    }
+}
+
+// An operator on the 4 register bits: y[r] = sum over present register
+// shifts M (main diagonal first, then ascending) of c_M[r] * v[r ^ M], with
+// the 16 coefficients of each present shift at c (uniform addresses: scalar
+// loads).  Every thread applies it to its own registers.
+template <typename T>
+__device__ __forceinline__ void reg_apply(Cx<T> (&v)[16], uint32_t present, const Cx<T> *__restrict__ c) {
+    Cx<T> y[16];
+    uint32_t t0 = 0;
+    if (present & 1u) {
+#pragma unroll
+        for (int r = 0; r < 16; r++) y[r] = cmul(c[r], v[r]);
+        t0 = 16;
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; r++) y[r] = Cx<T>{T(0), T(0)};
+    }
+    static_for<1, 16>([&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        if (present & (1u << M)) {
+#pragma unroll
+            for (int r = 0; r < 16; r++) cmac(y[r], c[t0 + r], v[r ^ M]);
+            t0 += 16;
+        }
+    });
+#pragma unroll
+    for (int r = 0; r < 16; r++) v[r] = y[r];
+}
+
+// The LDS byte address of every element of a thread under layout `pos`
+// (canonical bit per position): the tile's canonical index j sits at slot
+// sw(j), and the fold is linear, so the thread part and the register part
+// combine by XOR.
+template <typename T, int LOGT>
+__device__ __forceinline__ void reg_lds_addr(const uint8_t (&pos)[16], uint32_t (&addr)[16]) {
+    using L = LdsTile<T>;
+    const int tid = threadIdx.x;
+    int tj = 0;
+#pragma unroll
+    for (int bt = 0; bt < LOGT; bt++)
+        if ((tid >> bt) & 1) tj |= 1 << pos[bt];
+    const uint32_t stp = uint32_t(sw<T>(tj)) << L::LOGE;
+    uint32_t sib[4];
+#pragma unroll
+    for (int b = 0; b < 4; b++) sib[b] = uint32_t(sw<T>(1 << pos[LOGT + b])) << L::LOGE;
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+        uint32_t a = stp;
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+            if ((i >> b) & 1) a ^= sib[b];
+        addr[i] = a;
+    }
+}
+
+// The eight words of the record at LDS byte address `at`, in scalar
+// registers (every lane reads the same words).
+__device__ __forceinline__ void reg_rec(uint32_t at, uint32_t (&w)[8]) {
+    typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+    const U4 a = *reinterpret_cast<const __attribute__((address_space(3))) U4 *>(uintptr_t(at));
+    const U4 b = *reinterpret_cast<const __attribute__((address_space(3))) U4 *>(uintptr_t(at + 16));
+    const uint32_t x[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int i = 0; i < 8; i++) w[i] = __builtin_amdgcn_readfirstlane(x[i]);
+}
+
+__device__ __forceinline__ void rec_bytes(const uint32_t (&w)[8], uint8_t (&pos)[16]) {
+#pragma unroll
+    for (int x = 0; x < 16; x++) pos[x] = uint8_t((w[x >> 2] >> (8 * (x & 3))) & 0xff);
+}
+
+// LDS of a register-resident pass: the tile (only for passes with
+// re-layouts), then the pass's records, copied at the start so that a
+// record costs an LDS read instead of a trip to memory.
+template <typename T, int LOGT>
+__global__ void __launch_bounds__(1 << LOGT) k_reg(Cx<T> *__restrict__ state, uint64_t sstride, RegArgs ra,
+                                                  const DevOp *__restrict__ ops, uint32_t ob, uint32_t oe,
+                                                  const Cx<T> *__restrict__ coefs, uint32_t cb, uint32_t ce,
+                                                  uint64_t cstride, const int32_t *__restrict__ status,
+                                                  uint32_t flags) {
+    using L = LdsTile<T>;
+    constexpr int TNT = 1 << LOGT;
+    const uint32_t b = blockIdx.y;
+    if (status && status[b] != 0) return;
+    Cx<T> *st = state + size_t(b) * sstride;
+    const Cx<T> *cfs = coefs + size_t(b) * cstride;
+    const int tid = threadIdx.x;
+    const uint64_t base = deposit(blockIdx.x, ra.rest_mask);
+    const bool nt = (ra.flags & RF_NONTEMPORAL) != 0;
+    typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+    const uint32_t nrec = oe - ob;
+    const uint32_t rec_at = ra.lds_bytes - nrec * uint32_t(sizeof(DevOp));
+    // The pass's records: in flight first.  Its coefficients, read later
+    // through the scalar cache, are touched once here (one load per 64-byte
+    // line, spread over the workgroup) so that those reads find them in L2.
+    const U4 *gops = reinterpret_cast<const U4 *>(ops + ob);
+    U4 rv[2];
+#pragma unroll
+    for (int x = 0; x < 2; x++) {
+        const uint32_t idx = uint32_t(tid) + uint32_t(x) * TNT;
+        if (idx < 2 * nrec) rv[x] = gops[idx];
+    }
+    {
+        const char *c0 = reinterpret_cast<const char *>(cfs + cb);
+        const uint32_t lines = ((ce - cb) * uint32_t(sizeof(Cx<T>)) + 63) / 64;
+        for (uint32_t x = tid; x < lines; x += TNT) (void)*reinterpret_cast<const volatile uint32_t *>(c0 + 64 * size_t(x));
+    }
+    // global offsets of a thread's elements in the load layout
+    Cx<T> v[16];
+    {
+        uint64_t toff = 0;
+#pragma unroll
+        for (int bt = 0; bt < LOGT; bt++)
+            if ((tid >> bt) & 1) toff |= uint64_t(1) << ra.tq[ra.load_pos[bt]];
+        uint64_t ib[4];
+#pragma unroll
+        for (int x = 0; x < 4; x++) ib[x] = uint64_t(1) << ra.tq[ra.load_pos[LOGT + x]];
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+            uint64_t a = base | toff;
+#pragma unroll
+            for (int x = 0; x < 4; x++)
+                if ((i >> x) & 1) a |= ib[x];
+            if (flags & TF_INIT_ZERO) v[i] = Cx<T>{T(a == 0 ? 1 : 0), T(0)};
+            else v[i] = nt ? ld_stream(st + a) : st[a];
+        }
+    }
+#pragma unroll
+    for (int x = 0; x < 2; x++) {
+        const uint32_t idx = uint32_t(tid) + uint32_t(x) * TNT;
+        if (idx < 2 * nrec)
+            *reinterpret_cast<__attribute__((address_space(3))) U4 *>(uintptr_t(rec_at + 16u * idx)) = rv[x];
+    }
+    for (uint32_t idx = uint32_t(tid) + 2u * TNT; idx < 2 * nrec; idx += TNT)
+        *reinterpret_cast<__attribute__((address_space(3))) U4 *>(uintptr_t(rec_at + 16u * idx)) = gops[idx];
+    __syncthreads();
+    bool xposed = false;
+    for (uint32_t at = 0; at < nrec; at++) {
+        uint32_t w[8];
+        reg_rec(rec_at + at * uint32_t(sizeof(DevOp)), w);
+        const int kind = int((w[3] >> 16) & 0xff);
+        if (kind == qs::DEVOP_RMAT) {
+            uint32_t cf = w[0];
+            const uint32_t present = w[1];
+            const int kx = int(w[3] >> 24);
+            if (kx) {
+                // block qubits outside the tile select the coefficient block
+                const int xq[5] = {int((w[6] >> 16) & 0xff), int(w[6] >> 24), int(w[7] & 0xff),
+                                   int((w[7] >> 8) & 0xff), int((w[7] >> 16) & 0xff)};
+                uint32_t e = 0;
+#pragma unroll
+                for (int j = 0; j < 5; j++)
+                    if (j < kx) e |= uint32_t((base >> xq[j]) & 1) << j;
+                cf += (e * uint32_t(__builtin_popcount(present))) << 4;
+            }
+            reg_apply<T>(v, present, cfs + cf);
+        } else if (kind == qs::DEVOP_SWAP) {
+            const int lane = int((w[2] >> 8) & 0xff), rb = int((w[2] >> 16) & 0xff);
+            if (lane == 5) reg_swap_rb<T, true>(v, rb);
+            else reg_swap_rb<T, false>(v, rb);
+        } else if (kind == qs::DEVOP_XPOSE) {
+            // the tile through LDS: written in the layout of this record,
+            // read back in the layout of the next one
+            uint8_t from[16], to[16];
+            rec_bytes(w, from);
+            reg_rec(rec_at + (at + 1) * uint32_t(sizeof(DevOp)), w);
+            rec_bytes(w, to);
+            at++;
+            uint32_t addr[16];
+            reg_lds_addr<T, LOGT>(from, addr);
+            if (xposed) __syncthreads();   // every wave has read the previous layout
+#pragma unroll
+            for (int i = 0; i < 16; i++) L::st(addr[i], v[i]);
+            __syncthreads();
+            reg_lds_addr<T, LOGT>(to, addr);
+#pragma unroll
+            for (int i = 0; i < 16; i++) v[i] = L::ld(addr[i]);
+            xposed = true;
+        }
+    }
+    // store in the final layout
+    {
+        uint64_t toff = 0;
+#pragma unroll
+        for (int bt = 0; bt < LOGT; bt++)
+            if ((tid >> bt) & 1) toff |= uint64_t(1) << ra.tq[ra.store_pos[bt]];
+        uint64_t ib[4];
+#pragma unroll
+        for (int x = 0; x < 4; x++) ib[x] = uint64_t(1) << ra.tq[ra.store_pos[LOGT + x]];
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+            uint64_t a = base | toff;
+#pragma unroll
+            for (int x = 0; x < 4; x++)
+                if ((i >> x) & 1) a |= ib[x];
+            if (nt) st_stream(st + a, v[i]);
+            else st[a] = v[i];
+        }
+    }
+}
+
 // --------------------------------------------------------- strided sweep
 template <typename T, int K>
 __global__ void __launch_bounds__(NT) k_sweep(Cx<T> *__restrict__ state, uint64_t sstride, int n,
@@ -1064,9 +1311,26 @@ static void lds_attr() {
     if (hipFuncGetAttributes(&fa, f) == hipSuccess && fa.sharedSizeBytes != 0) tile_static_lds = 1;
 }
 
+template <typename T, int LOGT>
+static void reg_attr() {
+    const void *f = reinterpret_cast<const void *>(&k_reg<T, LOGT>);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(max_lds_bytes()));
+    if (e != hipSuccess) note_hip(e, "hipFuncSetAttribute(k_reg)");
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, f) == hipSuccess && fa.sharedSizeBytes != 0) tile_static_lds = 1;
+}
+
 int init_kernels() {
     static int done = 0;
     if (done) return QSIM_OK;
+    reg_attr<float, 6>();
+    reg_attr<float, 7>();
+    reg_attr<float, 8>();
+    reg_attr<float, 9>();
+    reg_attr<double, 6>();
+    reg_attr<double, 7>();
+    reg_attr<double, 8>();
+    reg_attr<double, 9>();
     // Allow the tile kernels the largest dynamic LDS they use (160 KiB).  The
     // attribute is advisory on this platform: a refusal is recorded, and a
     // launch that then asks for too much LDS reports its own error.
@@ -1169,6 +1433,48 @@ int launch_tile(int dtype, void *state, uint64_t sstride, uint32_t nstates, cons
                  ? tile_dispatch<float>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st)
                  : tile_dispatch<double>(state, sstride, nstates, ta, ops, ob, oe, coefs, cb, ce, cstride, m, flags, st);
     if (rc) return rc;
+    return check(hipGetLastError());
+}
+
+template <typename T, int LOGT>
+static void reg_t(void *state, uint64_t sstride, uint32_t nstates, const RegArgs &ra, const DevOp *ops,
+                  uint32_t ob, uint32_t oe, const void *coefs, uint32_t cb, uint32_t ce, uint64_t cstride,
+                  const int32_t *status, uint32_t flags, size_t lds, hipStream_t st) {
+    const dim3 grid(uint32_t(uint64_t(1) << (ra.n - ra.t)), nstates);
+    hipLaunchKernelGGL((k_reg<T, LOGT>), grid, dim3(1 << LOGT), lds, st, (Cx<T> *)state, sstride, ra, ops, ob,
+                       oe, (const Cx<T> *)coefs, cb, ce, cstride, status, flags);
+}
+
+size_t reg_lds_bytes(size_t elem, int t, bool relayouts, uint32_t nrec) {
+    return (relayouts ? (elem << t) : size_t(0)) + size_t(nrec) * sizeof(DevOp);
+}
+
+int launch_reg(int dtype, void *state, uint64_t sstride, uint32_t nstates, const RegArgs &ra,
+               const DevOp *ops, uint32_t ob, uint32_t oe, const void *coefs, uint32_t cb, uint32_t ce,
+               uint64_t cstride, const int32_t *status, uint32_t flags, hipStream_t st) {
+    const int logt = ra.t - 4;
+    const size_t elem = dtype == QSIM_C64 ? 8 : 16;
+    if (logt < 6 || logt > 9 || ra.t >= ra.n || ra.n - ra.t > 31 || oe < ob || ce < cb ||
+        (ra.lds_bytes != reg_lds_bytes(elem, ra.t, false, oe - ob) &&
+                                          ra.lds_bytes != reg_lds_bytes(elem, ra.t, true, oe - ob)))
+        return QSIM_E_ARG;
+    if (ra.lds_bytes > max_lds_bytes()) return QSIM_E_CAPACITY;
+    const size_t lds = ra.lds_bytes;
+    if (dtype == QSIM_C64) {
+        switch (logt) {
+        case 6: reg_t<float, 6>(state, sstride, nstates, ra, ops, ob, oe, coefs, cb, ce, cstride, status, flags, lds, st); break;
+        case 7: reg_t<float, 7>(state, sstride, nstates, ra, ops, ob, oe, coefs, cb, ce, cstride, status, flags, lds, st); break;
+        case 8: reg_t<float, 8>(state, sstride, nstates, ra, ops, ob, oe, coefs, cb, ce, cstride, status, flags, lds, st); break;
+        default: reg_t<float, 9>(state, sstride, nstates, ra, ops, ob, oe, coefs, cb, ce, cstride, status, flags, lds, st); break;
+        }
+    } else {
+        switch (logt) {
+        case 6: reg_t<double, 6>(state, sstride, nstates, ra, ops, ob, oe, coefs, cb, ce, cstride, status, flags, lds, st); break;
+        case 7: reg_t<double, 7>(state, sstride, nstates, ra, ops, ob, oe, coefs, cb, ce, cstride, status, flags, lds, st); break;
+        case 8: reg_t<double, 8>(state, sstride, nstates, ra, ops, ob, oe, coefs, cb, ce, cstride, status, flags, lds, st); break;
+        default: reg_t<double, 9>(state, sstride, nstates, ra, ops, ob, oe, coefs, cb, ce, cstride, status, flags, lds, st); break;
+        }
+    }
     return check(hipGetLastError());
 }
 

@@ -45,6 +45,33 @@ struct MeasArgs {
 
 enum : uint32_t { TF_INIT_ZERO = 1, TF_NO_STORE = 2 };
 
+// Register-resident pass (records DEVOP_RMAT / SWAP / XPOSE): canonical tile
+// bit c is qubit tq[c]; position p of an element index (lane bits 0..5, wave
+// bits 6..logt-1, register bits logt..logt+3) holds canonical bit
+// load_pos[p] as loaded and store_pos[p] as stored.  The workgroup has
+// 2^(t-4) threads.  LDS: the tile (2^t elements, only for a pass with LDS
+// re-layouts) and then the pass's records: lds_bytes = reg_lds_bytes(...).
+struct RegArgs {
+    uint64_t rest_mask;
+    int32_t n, t;
+    uint32_t lds_bytes;
+    uint32_t flags;          // RF_NONTEMPORAL: stream the state past the caches
+    uint8_t tq[16];
+    uint8_t load_pos[16];
+    uint8_t store_pos[16];
+};
+enum : uint32_t { RF_NONTEMPORAL = 1 };
+
+// One register-resident pass over `nstates` states spaced `sstride` apart;
+// records [ob, oe) of `ops`, coefficients of state b at coefs + b * cstride;
+// states whose status is nonzero are skipped; flags: TF_INIT_ZERO.
+// Records [ob, oe), coefficient range [cb, ce) of
+// the pass (elements; touched once at the start so that scalar reads hit L2).
+size_t reg_lds_bytes(size_t elem, int t, bool relayouts, uint32_t nrec);
+int launch_reg(int dtype, void *state, uint64_t sstride, uint32_t nstates, const RegArgs &ra,
+               const qs::DevOp *ops, uint32_t ob, uint32_t oe, const void *coefs, uint32_t cb, uint32_t ce,
+               uint64_t cstride, const int32_t *status, uint32_t flags, hipStream_t st);
+
 // Enable > 64 KiB of dynamic LDS for the tile kernels.  Idempotent.
 int init_kernels();
 size_t max_lds_bytes();

@@ -194,8 +194,8 @@ void place_positions(int n, const std::vector<Op> &ops, int logt, int max_k, boo
                      std::vector<Pass> *passes) {
     const uint64_t all = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
     for (Pass &p : *passes) {
-        if (!first_in_regs || p.kind != Pass::TILE || p.strided || p.tile_mask == all || p.t <= logt ||
-            p.ops.empty())
+        if (!first_in_regs || p.reg || p.kind != Pass::TILE || p.strided || p.tile_mask == all ||
+            p.t <= logt || p.ops.empty())
             continue;
         const uint64_t low = (uint64_t(1) << p.c) - 1;
         const int le = std::min(p.t - logt, 4);
@@ -280,7 +280,7 @@ uint64_t op_moved_qubits(const Op &o, uint32_t present) {
 }
 
 int pack_plan(const std::vector<Op> &ops, const std::vector<uint32_t> &present_of,
-              const std::vector<Pass> &passes, PackedPlan *out) {
+              std::vector<Pass> &passes, const PlanConfig &cfg, PackedPlan *out) {
     out->ops.clear();
     out->pass_begin.clear();
     out->coef_begin.clear();
@@ -288,9 +288,14 @@ int pack_plan(const std::vector<Op> &ops, const std::vector<uint32_t> &present_o
     out->op_np.clear();
     out->op_slots.clear();
     out->terms = 0;
-    for (const Pass &p : passes) {
+    for (Pass &p : passes) {
         out->pass_begin.push_back(uint32_t(out->ops.size()));
         out->coef_begin.push_back(uint32_t(out->coefs.size()));
+        if (p.reg) {
+            const int rc = pack_reg_pass(ops, present_of, p, cfg.reg_coalesce, out);
+            if (rc) return rc;
+            continue;
+        }
         const std::vector<int> &items = p.seq.empty() ? p.ops : p.seq;
         for (int idx : items) {
             if (idx < 0) {

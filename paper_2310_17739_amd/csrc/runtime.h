@@ -15,6 +15,8 @@ struct PassInfo {
     int kind = Pass::TILE;      // Pass::TILE, STRIDED or MEASURE
     bool strided = false;
     qk::TileArgs ta{};
+    bool reg = false;           // register-resident tiled pass (k_reg)
+    qk::RegArgs ra{};
     MeasRec meas;               // MEASURE passes
 };
 
@@ -22,6 +24,7 @@ struct Compiled {
     PackedPlan plan;
     std::vector<PassInfo> passes;
     qsim_apply_stats stats{};
+    int64_t stats_reg_swaps = 0, stats_reg_xposes = 0;   // register-resident passes
 };
 
 // Device copies of a packed plan with a pinned staging buffer.

@@ -21,7 +21,7 @@ LIB_PATH = os.environ.get("QSIM_LIB") or os.path.join(_HERE, "libqsim.so")
 C64, C128 = 1, 2
 OK, E_ARG, E_QUBIT, E_NOMEM, E_ZERO_PROB, E_NOT_DEFINITE, E_HIP, E_CAPACITY, E_UNSUPPORTED = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
-F_ONE_OP_PER_PASS, F_NO_SPARSE, F_FULL_SUPPORT = 1, 2, 4
+F_ONE_OP_PER_PASS, F_NO_SPARSE, F_FULL_SUPPORT, F_REG_ENGINE = 1, 2, 4, 8
 
 
 class QsimError(RuntimeError):
@@ -46,13 +46,16 @@ class qsim_fuse_opts(C.Structure):
 class qsim_apply_stats(C.Structure):
     _fields_ = [("input_gates", C.c_int64), ("ops_after", C.c_int64 * 6), ("fused_ops", C.c_int64),
                 ("passes", C.c_int64), ("terms", C.c_int64), ("bytes_moved", C.c_int64),
-                ("compile_seconds", C.c_double), ("tile_qubits", C.c_int32), ("max_width", C.c_int32)]
+                ("compile_seconds", C.c_double), ("tile_qubits", C.c_int32), ("max_width", C.c_int32),
+                ("reg_passes", C.c_int64), ("reg_swaps", C.c_int64), ("reg_relayouts", C.c_int64)]
 
     def as_dict(self):
         return {"input_gates": self.input_gates, "ops_after": list(self.ops_after),
                 "fused_ops": self.fused_ops, "passes": self.passes, "terms": self.terms,
                 "bytes_moved": self.bytes_moved, "compile_seconds": self.compile_seconds,
-                "tile_qubits": self.tile_qubits, "max_width": self.max_width}
+                "tile_qubits": self.tile_qubits, "max_width": self.max_width,
+                "reg_passes": self.reg_passes, "reg_swaps": self.reg_swaps,
+                "reg_relayouts": self.reg_relayouts}
 
 
 def _load():

@@ -72,3 +72,35 @@ def test_dense_matrices_wide_operators_and_single_operator_passes():
         got = qsim.qsim_debug_emulate(n, g, "complex64", mats=allm, psi=psi0, **kw)
         # random non-unitary factors: compare relative to the result's size
         check(got, want, rel=1e-10)
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+@pytest.mark.parametrize("n,tile", [(15, 10), (15, 11), (16, 12), (16, 13)])
+@pytest.mark.parametrize("gen", ["all_kinds", "pauli", "diagonal"])
+def test_register_resident_passes_equal_oracle(dtype, n, tile, gen):
+    """Tiles of 10..13 qubits run register-resident: every operator on the
+    four register bits, qubits swapped in from lane bits 4 and 5, LDS
+    re-layouts otherwise.  The emulation moves the elements exactly as the
+    kernel does (position bits, lane/register exchanges, re-layouts checked
+    against the layout the records before them leave)."""
+    if gen == "all_kinds":
+        g = W.random_all_kinds(n, 250, seed=n + tile, max_arity=4)
+    elif gen == "pauli":
+        g, _, _ = W.pauli_exponential_circuit(n, 120, seed=n + tile)
+    else:
+        g = W.diagonal_rich_circuit(n, 250, seed=n + tile, p_diag=0.7)
+    psi0 = W.random_state(n, tile)
+    want, _, _ = oracle.run(n, g, psi=psi0)
+    st = qsim.qsim_debug_plan(n, g, dtype, tile_qubits=tile, flags=qsim.F_REG_ENGINE)
+    assert st["reg_passes"] == st["passes"] > 0
+    check(qsim.qsim_debug_emulate(n, g, dtype, tile_qubits=tile, psi=psi0, flags=qsim.F_REG_ENGINE), want)
+
+
+def test_register_programs_use_swaps_and_relayouts():
+    """On the benchmark-style circuit both ways of bringing a qubit onto the
+    register bits occur, and low qubits are restored before the store."""
+    g, _, _ = W.pauli_exponential_circuit(18, 400, seed=9)
+    st = qsim.qsim_debug_plan(18, g, "complex128", flags=qsim.F_REG_ENGINE)
+    assert st["reg_passes"] == st["passes"]
+    assert qsim.qsim_debug_plan(18, g, "complex128")["reg_passes"] == 0
+    assert st["reg_swaps"] > 0 and st["reg_relayouts"] > 0
