@@ -70,7 +70,10 @@ enum {
     QSIM_G_CX = 20, QSIM_G_CY = 21, QSIM_G_CZ = 22, QSIM_G_CH = 23,
     QSIM_G_SWAP = 24, QSIM_G_CRX = 25, QSIM_G_CRY = 26, QSIM_G_CRZ = 27,
     QSIM_G_CU1 = 28, QSIM_G_CU3 = 29, QSIM_G_RXX = 30, QSIM_G_RZZ = 31,
-    QSIM_G_CCX = 40, QSIM_G_CSWAP = 41, QSIM_G_C3X = 44, QSIM_G_C3XSQRTX = 45,
+    QSIM_G_CCX = 40, QSIM_G_CSWAP = 41,
+    QSIM_G_RCCX = 42,     /* relative-phase Toffoli (OpenQASM rccx): CCX up to a diagonal */
+    QSIM_G_RC3X = 43,     /* relative-phase 3-controlled X (OpenQASM rc3x) */
+    QSIM_G_C3X = 44, QSIM_G_C3XSQRTX = 45,
     QSIM_G_C4X = 46,
     QSIM_G_MAT = 50,      /* 2^nq x 2^nq complex128 matrix from the pool */
     QSIM_G_BARRIER = 60,  /* fusion fence */
@@ -298,7 +301,10 @@ typedef struct qsim_batch_opts {
     int32_t dtype;           /* QSIM_C64 or QSIM_C128 */
     int32_t use_graph;       /* 1: record the whole run once as a HIP graph and replay it */
     int32_t max_params;      /* angle slots per fused operator (0 = 2) */
-    int32_t pad;
+    int32_t autotune;        /* 1: per group, time fusion widths 2..5 (complex128: 2..4) on
+                                the template with state 0's angles bound, on a scratch
+                                state allocated for the purpose, and compile the group
+                                with the fastest; the other fields of `fuse` are kept */
     qsim_fuse_opts fuse;     /* level 0 selects the default (5) */
 } qsim_batch_opts;
 
@@ -309,7 +315,8 @@ typedef struct qsim_batch_info {
     int64_t passes;          /* summed over groups */
     int64_t state_bytes;
     int64_t coef_bytes;
-    double compile_seconds;
+    double compile_seconds;  /* includes tune_seconds */
+    double tune_seconds;     /* time spent by the autotuner (0 without it) */
 } qsim_batch_info;
 
 /* Compile every group once (lowering, fusion, plan; angle-dependent
@@ -329,6 +336,9 @@ int qsim_batch_results(qsim_batch_h b, int group, int32_t *outcomes, double *pro
                        double *expvals, double *norms, int32_t *status);
 int qsim_batch_get_state(qsim_batch_h b, int group, int index, void *host_dst);
 int qsim_batch_info_get(qsim_batch_h b, qsim_batch_info *out);
+/* Compile statistics of one group (fused operators, passes, fusion width
+ * used) and the width the autotuner chose for it (0 if not tuned). */
+int qsim_batch_group_stats(qsim_batch_h b, int group, qsim_apply_stats *out, int32_t *tuned_width);
 int qsim_batch_destroy(qsim_batch_h b);
 
 /* ----------------------------------------------------------- serving */
@@ -378,6 +388,7 @@ typedef struct qsim_result {
 typedef struct qsim_server_stats {
     int64_t submitted, completed, rejected, in_flight, waiting;
     size_t pool_bytes, pool_in_use, pool_peak;
+    int64_t peak_in_flight;   /* most requests admitted (resident on the device) at once */
 } qsim_server_stats;
 
 /* Errors: QSIM_E_ARG, QSIM_E_NOMEM (pool allocation), QSIM_E_HIP. */
@@ -490,6 +501,14 @@ int qsim_debug_emulate(int n, int dtype, const qsim_gate *g, size_t ng, const do
 int qsim_debug_plan(int n, int dtype, const qsim_gate *g, size_t ng,
                     const double *mats, size_t n_mats, const double *params,
                     size_t n_params, const qsim_fuse_opts *opt, qsim_apply_stats *out);
+
+/* Test hook for the out-of-memory paths: the allocation attempt `after`
+ * attempts from now (0 = the next one) fails as if the device or host were
+ * out of memory, once; -1 disarms.  Counted attempts: every device and
+ * pinned-host allocation the library makes and the start of every compile
+ * (standing for its host allocations).  The failing call returns
+ * QSIM_E_NOMEM and leaves the state and the handle as they were. */
+int qsim_debug_fail_alloc(int after);
 
 const char *qsim_strerror(int status);
 /* Text of the last failed HIP call on this thread (empty if none). */

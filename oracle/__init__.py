@@ -31,6 +31,9 @@ from workloads import GATE_DTYPE, PAULI_DTYPE
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# a prebuilt variant of the same source (the sanitizer build) may be named
+# instead; it is then loaded as is
+_LIB_OVERRIDE = os.environ.get("ORACLE_LIB")
 
 E_OK, E_ARG, E_QUBIT, E_ZERO_PROB, E_NOT_DEFINITE = 0, -1, -2, -4, -5
 
@@ -55,11 +58,25 @@ def build(force: bool = False) -> str:
 _lib = None
 
 
+def build_sanitized(out: str) -> str:
+    """Compile oracle.c with clang's AddressSanitizer and UBSan (shared
+    sanitizer runtime) into `out`, for host-side checks of the oracle."""
+    clang = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "llvm", "bin", "clang")
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    subprocess.check_call([clang, "-O1", "-g", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                           "-shared-libsan", "-fno-omit-frame-pointer", "-o", out, _SRC, "-lm"])
+    return out
+
+
 def _load():
     global _lib
     if _lib is None:
-        build()
-        lib = C.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            lib = C.CDLL(_LIB_OVERRIDE)
+        else:
+            build()
+            lib = C.CDLL(_LIB)
         P = C.c_void_p
         lib.orc_run.argtypes = [C.c_int, P, P, C.c_int64, P, P, P, P, P, P, P]
         lib.orc_run.restype = C.c_int

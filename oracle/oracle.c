@@ -45,7 +45,7 @@ enum {
     G_U2 = 14, G_U3 = 15,
     G_CX = 20, G_CY = 21, G_CZ = 22, G_CH = 23, G_SWAP = 24, G_CRX = 25,
     G_CRY = 26, G_CRZ = 27, G_CU1 = 28, G_CU3 = 29, G_RXX = 30, G_RZZ = 31,
-    G_CCX = 40, G_CSWAP = 41, G_C3X = 44, G_C3XSQRTX = 45, G_C4X = 46,
+    G_CCX = 40, G_CSWAP = 41, G_RCCX = 42, G_RC3X = 43, G_C3X = 44, G_C3XSQRTX = 45, G_C4X = 46,
     G_MAT = 50,
     G_BARRIER = 60, G_MEASURE = 61, G_RESET = 62, G_ASSERT0 = 63
 };
@@ -90,6 +90,46 @@ static int one_qubit_matrix(int kind, const double *t, cplx m[4]) {
     case G_U2: u3_matrix(M_PI / 2, t[0], t[1], m); return 1;
     case G_U3: u3_matrix(t[0], t[1], t[2], m); return 1;
     default: return 0;
+    }
+}
+
+/* The relative-phase Toffolis of OpenQASM's standard library are defined
+ * there as gate sequences on the target (the last local bit) and the
+ * controls; each step below is (kind, qubit) for a single-qubit gate, or
+ * (G_CX, control) for a CNOT onto the target.  u2(0, pi) is H and u1(+-pi/4)
+ * is T / T^dagger. */
+typedef struct { int kind, q; } seq_step;
+static const seq_step RCCX_SEQ[] = {
+    {G_H, 2}, {G_T, 2}, {G_CX, 1}, {G_TDG, 2}, {G_CX, 0}, {G_T, 2}, {G_CX, 1}, {G_TDG, 2}, {G_H, 2}};
+static const seq_step RC3X_SEQ[] = {
+    {G_H, 3}, {G_T, 3}, {G_CX, 2}, {G_TDG, 3}, {G_H, 3}, {G_CX, 0}, {G_T, 3}, {G_CX, 1}, {G_TDG, 3},
+    {G_CX, 0}, {G_T, 3}, {G_CX, 1}, {G_TDG, 3}, {G_H, 3}, {G_T, 3}, {G_CX, 2}, {G_TDG, 3}, {G_H, 3}};
+
+/* m = S_last ... S_1 for the steps of a sequence on k local bits (target =
+ * local bit k-1): every column of the identity is pushed through the steps. */
+static void sequence_matrix(const seq_step *seq, int ns, int k, cplx *m) {
+    const int dim = 1 << k, tgt = k - 1;
+    cplx col[32], nxt[32];
+    for (int c = 0; c < dim; c++) {
+        for (int r = 0; r < dim; r++) col[r] = (r == c) ? 1 : 0;
+        for (int s = 0; s < ns; s++) {
+            for (int r = 0; r < dim; r++) nxt[r] = 0;
+            if (seq[s].kind == G_CX) {
+                for (int r = 0; r < dim; r++)
+                    nxt[((r >> seq[s].q) & 1) ? (r ^ (1 << tgt)) : r] += col[r];
+            } else {
+                cplx u[4];
+                one_qubit_matrix(seq[s].kind, NULL, u);
+                const int b = seq[s].q;
+                for (int r = 0; r < dim; r++) {
+                    const int bit = (r >> b) & 1;
+                    nxt[r & ~(1 << b)] += u[0 * 2 + bit] * col[r];   /* row 0 of u, column bit */
+                    nxt[r | (1 << b)] += u[1 * 2 + bit] * col[r];    /* row 1 of u */
+                }
+            }
+            for (int r = 0; r < dim; r++) col[r] = nxt[r];
+        }
+        for (int r = 0; r < dim; r++) m[r * dim + c] = col[r];
     }
 }
 
@@ -166,6 +206,14 @@ static int gate_matrix(const orc_gate *g, const double *theta, cplx *m) {
             }
         }
         return k;
+    }
+    if (k == 3 && g->kind == G_RCCX) {
+        sequence_matrix(RCCX_SEQ, (int)(sizeof(RCCX_SEQ) / sizeof(RCCX_SEQ[0])), 3, m);
+        return 3;
+    }
+    if (k == 4 && g->kind == G_RC3X) {
+        sequence_matrix(RC3X_SEQ, (int)(sizeof(RC3X_SEQ) / sizeof(RC3X_SEQ[0])), 4, m);
+        return 4;
     }
     if (k == 3 && g->kind == G_CSWAP) {
         /* control = local bit 0; swap local bits 1 and 2 when it is set */

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
@@ -28,6 +29,20 @@ int note_hip(hipError_t e, const char *where) {
     return QSIM_E_HIP;
 }
 }  // namespace qk
+
+namespace qs {
+
+std::atomic<int> g_alloc_countdown{-1};
+
+bool alloc_fault() {
+    int v = g_alloc_countdown.load();
+    while (v >= 0) {
+        if (g_alloc_countdown.compare_exchange_weak(v, v - 1)) return v == 0;
+    }
+    return false;
+}
+
+}  // namespace qs
 
 namespace qs {
 
@@ -277,6 +292,7 @@ int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const GateI
                     bool keep_params, bool allow_meas, int max_params,
                     const qsim_fuse_opts *opt, Compiled *out) {
     double t0 = now_seconds();
+    if (alloc_fault()) throw std::bad_alloc();
     FuseConfig fc;
     PlanConfig pc;
     default_configs(n, dtype, opt, &fc, &pc);
@@ -382,6 +398,7 @@ int hip_rc(hipError_t e) { return qk::note_hip(e, "runtime call"); }
 
 int grow(void **ptr, size_t *cap, size_t need, hipStream_t st) {
     if (need <= *cap) return QSIM_OK;
+    if (qs::alloc_fault()) return QSIM_E_NOMEM;   // before anything is freed
     if (*ptr) {
         (void)hipStreamSynchronize(st);
         (void)hipFree(*ptr);
@@ -398,6 +415,7 @@ int grow(void **ptr, size_t *cap, size_t need, hipStream_t st) {
 
 int grow_host(void **ptr, size_t *cap, size_t need) {
     if (need <= *cap) return QSIM_OK;
+    if (qs::alloc_fault()) return QSIM_E_NOMEM;
     if (*ptr) (void)hipHostFree(*ptr);
     *ptr = nullptr;
     *cap = 0;
@@ -570,6 +588,12 @@ int weights01(qsim_h h, int q, double *P0, double *P1) {
 extern "C" {
 
 int qsim_version(void) { return 1; }
+
+int qsim_debug_fail_alloc(int after) {
+    if (after < -1) return QSIM_E_ARG;
+    qs::g_alloc_countdown.store(after);
+    return QSIM_OK;
+}
 
 const char *qsim_last_error(void) { return g_last_error; }
 
@@ -894,18 +918,19 @@ int qsim_expval(qsim_h h, const qsim_pauli *t, size_t nt, double *out) {
     if (rc) return rc;
     if (!(nrm > 0)) return QSIM_E_ZERO_PROB;
     if (nt == 0) { *out = 0.0; return QSIM_OK; }
-    rc = grow(&h->d_masks, &h->cap_masks, 16 * nt, h->stream);
+    std::vector<uint64_t> table;
+    const uint32_t nrows = qk::pauli_rows(t, nt, &table);
+    rc = grow(&h->d_masks, &h->cap_masks, 8 * table.size(), h->stream);
     if (rc) return rc;
-    std::vector<uint64_t> masks(2 * nt);
-    for (size_t k = 0; k < nt; k++) { masks[k] = t[k].xmask; masks[nt + k] = t[k].zmask; }
     uint64_t *dm = (uint64_t *)h->d_masks;
-    if (hipMemcpyAsync(dm, masks.data(), 16 * nt, hipMemcpyHostToDevice, h->stream) != hipSuccess)
+    // pageable source: the copy has left `table` when the call returns
+    if (hipMemcpyAsync(dm, table.data(), 8 * table.size(), hipMemcpyHostToDevice, h->stream) != hipSuccess)
         return QSIM_E_HIP;
     const uint32_t nch = qk::pauli_chunks(h->n);
     double *part, *dout;
     rc = reduce_buffers(h, size_t(nch) * 2 * nt, 2 * nt, &part, &dout);
     if (rc) return rc;
-    rc = qk::launch_pauli(h->dtype, h->buf, 0, 1, h->n, dm, dm + nt, int(nt), part, dout, h->stream);
+    rc = qk::launch_pauli(h->dtype, h->buf, 0, 1, h->n, dm, int(nt), nrows, part, dout, h->stream);
     if (rc) return rc;
     if (hipMemcpyAsync(h->h_out, dout, 2 * nt * sizeof(double), hipMemcpyDeviceToHost, h->stream) !=
         hipSuccess)
@@ -986,7 +1011,7 @@ int qsim_autotune(qsim_h h, const qsim_gate *g, size_t ng, const double *mats, s
     const int wmax = h->dtype == QSIM_C64 ? 5 : 4;
     for (int t : {tdef - 1, tdef, tdef + 1}) {
         if (t > resident_max(h->dtype)) continue;
-        for (int w = 3; w <= wmax; w++)
+        for (int w = 2; w <= wmax; w++)
             for (float cost : {2.0f, 4.0f, 8.0f})
                 for (int low : {ldef - 1, ldef}) {
                     qsim_fuse_opts o{};
@@ -1036,6 +1061,74 @@ int qsim_autotune(qsim_h h, const qsim_gate *g, size_t ng, const double *mats, s
     return rc;
 }
 
+}  // extern "C"
+
+namespace qs {
+
+int tune_width(int n, int dtype, const qsim_gate *g, size_t ng, const GateInputs &in,
+               const qsim_fuse_opts *base, int *best_w, double *best_ns) {
+    const int wmax = dtype == QSIM_C64 ? 5 : 4;
+    const size_t bytes = elem_bytes(dtype) << n;
+    void *buf = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = hip_rc(hipMalloc(&buf, bytes));
+    if (rc) return QSIM_E_NOMEM;
+    if (!rc) rc = hip_rc(hipStreamCreate(&st));
+    if (!rc) rc = hip_rc(hipEventCreate(&e0));
+    if (!rc) rc = hip_rc(hipEventCreate(&e1));
+    DeviceTables dt;
+    *best_w = 0;
+    *best_ns = 1e300;
+    for (int w = 2; w <= wmax && !rc; w++) {
+        qsim_fuse_opts o{};
+        if (base) o = *base;
+        o.level = 5;
+        o.max_width = w;
+        Compiled c;
+        try {
+            rc = compile_circuit(n, dtype, g, ng, in, &o, &c);
+        } catch (const std::bad_alloc &) {
+            rc = QSIM_E_NOMEM;
+        }
+        if (rc) break;
+        if (c.plan.ops.empty()) {
+            *best_w = w;
+            *best_ns = 0.0;
+            break;
+        }
+        if ((rc = upload_plan(&dt, dtype, c.plan, st))) break;
+        // warm, then the best of three timed runs
+        if ((rc = enqueue_passes(c, dt, dtype, buf, st, true))) break;
+        double best_run = 1e300;
+        for (int rep = 0; rep < 3 && !rc; rep++) {
+            (void)hipEventRecord(e0, st);
+            if ((rc = enqueue_passes(c, dt, dtype, buf, st, true))) break;
+            (void)hipEventRecord(e1, st);
+            if ((rc = hip_rc(hipEventSynchronize(e1)))) break;
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            best_run = std::min(best_run, double(ms));
+        }
+        const double ns = 1e6 * best_run / double(std::max<int64_t>(1, c.stats.input_gates));
+        if (!rc && ns < *best_ns) {
+            *best_ns = ns;
+            *best_w = w;
+        }
+    }
+    if (st) (void)hipStreamSynchronize(st);
+    free_tables(&dt);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    (void)hipFree(buf);
+    return rc;
+}
+
+}  // namespace qs
+
+extern "C" {
+
 int qsim_debug_fuse(int n, const qsim_gate *g, size_t ng, const double *mats, size_t n_mats,
                     const double *params, size_t n_params, const qsim_fuse_opts *opt, int32_t *out_k, int32_t *out_qubits,
                     double *out_mats, size_t cap_ops, size_t cap_doubles, size_t *n_ops,
@@ -1049,6 +1142,7 @@ int qsim_debug_fuse(int n, const qsim_gate *g, size_t ng, const double *mats, si
     int rc;
     int64_t cnt[6];
     try {
+        if (alloc_fault()) throw std::bad_alloc();
         rc = lower(n, g, ng, GateInputs{mats, n_mats, params, n_params}, false, false, &L);
         if (rc) return rc;
         fuse(n, &L, fc, cnt);

@@ -25,6 +25,7 @@ template <typename P>
 int dalloc(P **p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) return QSIM_OK;
+    if (alloc_fault()) return QSIM_E_NOMEM;
     void *v = nullptr;
     hipError_t e = hipMalloc(&v, bytes);
     if (e != hipSuccess) { qk::note_hip(e, "hipMalloc (batch)"); return QSIM_E_NOMEM; }
@@ -66,8 +67,10 @@ struct Group {
     double *d_norm = nullptr;      // [nstates]
     uint64_t *d_masks = nullptr;   // [2][nterms]
     double *d_pauli = nullptr;     // [nstates][nterms][2]
-    uint32_t pauli_chunks = 0, norm_chunks = 0;
+    uint32_t pauli_chunks = 0, norm_chunks = 0, pauli_rows = 0;
     int64_t coef_bytes = 0;
+    int tuned_width = 0;           // fusion width the autotuner chose (0: not tuned)
+    double tune_seconds = 0.0;
 };
 
 void free_group(Group &g) {
@@ -155,6 +158,32 @@ int setup_group(Group &G, const qsim_batch_group &in, int dtype, const qsim_batc
     const size_t elem = elem_bytes(dtype);
     const bool param = in.params != nullptr && in.n_params > 0;
     const qsim_fuse_opts *fo = (opt.fuse.level > 0) ? &opt.fuse : nullptr;
+    qsim_fuse_opts tuned{};
+    if (opt.autotune) {
+        // the template's fusion width, timed on its first instance (angles of
+        // state 0 bound on the host); measurement records are left out of the
+        // timed circuit, and the tile and low-qubit choices stay those of
+        // `opt.fuse`
+        std::vector<qsim_gate> timed;
+        timed.reserve(in.ng);
+        for (size_t i = 0; i < in.ng; i++)
+            if (in.g[i].kind != QSIM_G_MEASURE && in.g[i].kind != QSIM_G_ASSERT0 && in.g[i].kind != QSIM_G_RESET)
+                timed.push_back(in.g[i]);
+        int w = 0;
+        double ns = 0.0;
+        const double t0 = now_seconds();
+        int rc = tune_width(in.n, dtype, timed.data(), timed.size(),
+                            GateInputs{in.mats, in.mats ? in.n_mats : 0, param ? in.params : nullptr,
+                                       param ? size_t(in.n_params) : 0},
+                            fo, &w, &ns);
+        G.tune_seconds = now_seconds() - t0;
+        if (rc) return rc;
+        if (fo) tuned = *fo;
+        tuned.level = 5;
+        tuned.max_width = w;
+        fo = &tuned;
+        G.tuned_width = w;
+    }
     int rc = compile_program(in.n, dtype, in.g, in.ng,
                              GateInputs{in.mats, in.mats ? in.n_mats : 0, nullptr,
                                         param ? size_t(in.n_params) : 0},
@@ -243,12 +272,10 @@ int setup_group(Group &G, const qsim_batch_group &in, int dtype, const qsim_batc
         part = std::max(part, size_t(G.nstates) * G.nterms * 2 * G.pauli_chunks);
         G.terms.assign(in.terms, in.terms + G.nterms);
         const uint64_t lim = (uint64_t(1) << G.n) - 1;
-        std::vector<uint64_t> masks(2 * G.nterms);
-        for (size_t k = 0; k < G.nterms; k++) {
+        for (size_t k = 0; k < G.nterms; k++)
             if ((in.terms[k].xmask & ~lim) || (in.terms[k].zmask & ~lim)) return QSIM_E_ARG;
-            masks[k] = in.terms[k].xmask;
-            masks[G.nterms + k] = in.terms[k].zmask;
-        }
+        std::vector<uint64_t> masks;
+        G.pauli_rows = qk::pauli_rows(in.terms, G.nterms, &masks);
         if ((rc = dalloc(&G.d_masks, masks.size() * 8))) return rc;
         if ((rc = hip_ok(hipMemcpy(G.d_masks, masks.data(), masks.size() * 8, hipMemcpyHostToDevice), "masks"))) return rc;
         if ((rc = dalloc(&G.d_pauli, size_t(G.nstates) * G.nterms * 2 * 8))) return rc;
@@ -317,7 +344,7 @@ int enqueue_group(const Group &G, int dtype, hipStream_t st) {
     if (rc) return rc;
     if (G.nterms) {
         rc = qk::launch_pauli(dtype, G.d_states, G.sstride, uint32_t(G.nstates), G.n, G.d_masks,
-                              G.d_masks + G.nterms, int(G.nterms), G.d_part, G.d_pauli, st, G.pauli_chunks);
+                              int(G.nterms), G.pauli_rows, G.d_part, G.d_pauli, st, G.pauli_chunks);
         if (rc) return rc;
     }
     return QSIM_OK;
@@ -366,6 +393,7 @@ int qsim_batch_create(const qsim_batch_group *groups, int n_groups, const qsim_b
                 b->info.input_gates += G.c.stats.input_gates * G.nstates;
                 b->info.fused_ops += G.c.stats.fused_ops;
                 b->info.passes += G.c.stats.passes;
+                b->info.tune_seconds += G.tune_seconds;
                 b->info.state_bytes += int64_t(G.nstates) * int64_t(G.sstride * elem_bytes(o.dtype));
                 b->info.coef_bytes += G.coef_bytes;
             }
@@ -458,6 +486,13 @@ int qsim_batch_get_state(qsim_batch_h b, int group, int index, void *dst) {
     return hip_ok(hipMemcpy(dst, (char *)G.d_states + size_t(index) * G.sstride * e, G.sstride * e,
                             hipMemcpyDeviceToHost),
                   "get state");
+}
+
+int qsim_batch_group_stats(qsim_batch_h b, int group, qsim_apply_stats *out, int32_t *tuned_width) {
+    if (!b || !out || group < 0 || size_t(group) >= b->groups.size()) return QSIM_E_ARG;
+    *out = b->groups[size_t(group)].c.stats;
+    if (tuned_width) *tuned_width = b->groups[size_t(group)].tuned_width;
+    return QSIM_OK;
 }
 
 int qsim_batch_info_get(qsim_batch_h b, qsim_batch_info *out) {

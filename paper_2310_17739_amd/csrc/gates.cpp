@@ -124,8 +124,8 @@ int kind_arity(int kind) {
     case QSIM_G_CX: case QSIM_G_CY: case QSIM_G_CZ: case QSIM_G_CH: case QSIM_G_SWAP:
     case QSIM_G_CRX: case QSIM_G_CRY: case QSIM_G_CRZ: case QSIM_G_CU1: case QSIM_G_CU3:
     case QSIM_G_RXX: case QSIM_G_RZZ: return 2;
-    case QSIM_G_CCX: case QSIM_G_CSWAP: return 3;
-    case QSIM_G_C3X: case QSIM_G_C3XSQRTX: return 4;
+    case QSIM_G_CCX: case QSIM_G_CSWAP: case QSIM_G_RCCX: return 3;
+    case QSIM_G_C3X: case QSIM_G_C3XSQRTX: case QSIM_G_RC3X: return 4;
     case QSIM_G_C4X: return 5;
     default: return 0;
     }
@@ -140,6 +140,57 @@ bool is_half_angle_linear(int kind) {
     default: return false;
     }
 }
+
+// A gate given as a circuit on its k local bits (the relative-phase Toffolis
+// of OpenQASM's standard library): the product of the steps, last step
+// leftmost, built by multiplying each step's k-bit operator onto the
+// accumulated matrix.  A step is a single-qubit kind on local bit `a`, or a
+// CNOT from local bit `a` to local bit `b` (kind QSIM_G_CX).
+struct Step {
+    int kind, a, b;
+};
+
+void circuit_matrix(const Step *steps, int ns, int k, std::vector<cd> *m) {
+    const int d = 1 << k;
+    m->assign(size_t(d) * d, cd(0));
+    for (int i = 0; i < d; i++) (*m)[size_t(i) * d + i] = 1;
+    std::vector<cd> g(size_t(d) * d), acc(size_t(d) * d);
+    for (int s = 0; s < ns; s++) {
+        std::fill(g.begin(), g.end(), cd(0));
+        if (steps[s].kind == QSIM_G_CX) {
+            for (int c = 0; c < d; c++) {
+                const int r = ((c >> steps[s].a) & 1) ? (c ^ (1 << steps[s].b)) : c;
+                g[size_t(r) * d + c] = 1;
+            }
+        } else {
+            cd u[4];
+            one_qubit(steps[s].kind, nullptr, u);
+            const int a = steps[s].a;
+            for (int c = 0; c < d; c++)
+                for (int rb = 0; rb < 2; rb++) {
+                    const int r = (c & ~(1 << a)) | (rb << a);
+                    g[size_t(r) * d + c] = u[rb * 2 + ((c >> a) & 1)];
+                }
+        }
+        for (int r = 0; r < d; r++)
+            for (int c = 0; c < d; c++) {
+                cd v = 0;
+                for (int x = 0; x < d; x++) v += g[size_t(r) * d + x] * (*m)[size_t(x) * d + c];
+                acc[size_t(r) * d + c] = v;
+            }
+        m->swap(acc);
+    }
+}
+
+// OpenQASM's rccx a, b, c and rc3x a, b, c, d (controls first, target last)
+const Step kRccx[] = {{QSIM_G_H, 2, 0},   {QSIM_G_T, 2, 0},  {QSIM_G_CX, 1, 2}, {QSIM_G_TDG, 2, 0},
+                      {QSIM_G_CX, 0, 2},  {QSIM_G_T, 2, 0},  {QSIM_G_CX, 1, 2}, {QSIM_G_TDG, 2, 0},
+                      {QSIM_G_H, 2, 0}};
+const Step kRc3x[] = {{QSIM_G_H, 3, 0},   {QSIM_G_T, 3, 0},   {QSIM_G_CX, 2, 3}, {QSIM_G_TDG, 3, 0},
+                      {QSIM_G_H, 3, 0},   {QSIM_G_CX, 0, 3},  {QSIM_G_T, 3, 0},  {QSIM_G_CX, 1, 3},
+                      {QSIM_G_TDG, 3, 0}, {QSIM_G_CX, 0, 3},  {QSIM_G_T, 3, 0},  {QSIM_G_CX, 1, 3},
+                      {QSIM_G_TDG, 3, 0}, {QSIM_G_H, 3, 0},   {QSIM_G_T, 3, 0},  {QSIM_G_CX, 2, 3},
+                      {QSIM_G_TDG, 3, 0}, {QSIM_G_H, 3, 0}};
 
 }  // namespace
 
@@ -165,6 +216,8 @@ int gate_matrix(const qsim_gate &g, const double *t, std::vector<cd> *m) {
     case QSIM_G_C3X: one_qubit(QSIM_G_X, t, u); controlled(u, 3, m); return QSIM_OK;
     case QSIM_G_C4X: one_qubit(QSIM_G_X, t, u); controlled(u, 4, m); return QSIM_OK;
     case QSIM_G_C3XSQRTX: one_qubit(QSIM_G_SX, t, u); controlled(u, 3, m); return QSIM_OK;
+    case QSIM_G_RCCX: circuit_matrix(kRccx, int(sizeof(kRccx) / sizeof(kRccx[0])), 3, m); return QSIM_OK;
+    case QSIM_G_RC3X: circuit_matrix(kRc3x, int(sizeof(kRc3x) / sizeof(kRc3x[0])), 4, m); return QSIM_OK;
     case QSIM_G_RXX: pauli_rotation("XX", 2, t[0], m); return QSIM_OK;
     case QSIM_G_RZZ: pauli_rotation("ZZ", 2, t[0], m); return QSIM_OK;
     case QSIM_G_SWAP:

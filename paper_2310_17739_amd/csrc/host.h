@@ -243,4 +243,10 @@ int pack_reg_pass(const std::vector<Op> &ops, const std::vector<uint32_t> &prese
 
 double now_seconds();
 
+// Allocation-failure injection for tests (qsim_debug_fail_alloc): true when
+// this allocation attempt is the one set to fail.  Every device and pinned
+// allocation of the library, and the start of every compile (standing for
+// its host allocations), asks once.
+bool alloc_fault();
+
 }  // namespace qs

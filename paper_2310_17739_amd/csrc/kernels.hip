@@ -21,9 +21,11 @@
 // results are bit-identical from run to run.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <mutex>
+#include <vector>
 
 #include "launch.h"
 #include "swizzle.h"
@@ -1092,31 +1094,50 @@ __global__ void __launch_bounds__(NT) k_marginal(const Cx<T> *__restrict__ state
         partials[(size_t(blockIdx.z) * gridDim.y + bin) * nchunks + chunk] = acc[0];
 }
 
+// Pauli overlaps of up to kPauliRow terms that share an X mask (one row of
+// the table built by pauli_rows): each amplitude pair (a[x], a[x ^ X]) is
+// read once and its product conj(a[x ^ X]) a[x] added, with the sign
+// (-1)^popcount(x & z_k), to every term k of the row.  Each term's sums run
+// in the same order as they would alone.
 // partials[((b * nterms + k) * 2 + comp) * nchunks + chunk]
 template <typename T>
 __global__ void __launch_bounds__(NT) k_pauli(const Cx<T> *__restrict__ state, uint64_t sstride,
-                                              int n, const uint64_t *__restrict__ xmask,
-                                              const uint64_t *__restrict__ zmask,
+                                              int n, const uint64_t *__restrict__ zmask,
+                                              const uint64_t *__restrict__ rows, uint32_t nterms,
                                               double *__restrict__ partials) {
     const Cx<T> *st = state + size_t(blockIdx.z) * sstride;
-    const uint32_t k = blockIdx.y, chunk = blockIdx.x, nchunks = gridDim.x;
-    const uint64_t xm = xmask[k], zm = zmask[k];
+    const uint32_t chunk = blockIdx.x, nchunks = gridDim.x;
+    const uint64_t *row = rows + size_t(blockIdx.y) * (2 + kPauliRow);
+    const uint64_t xm = row[0];
+    const int cnt = int(row[1]);
+    uint64_t z[kPauliRow];
+#pragma unroll
+    for (int j = 0; j < kPauliRow; j++) z[j] = j < cnt ? zmask[row[2 + j]] : 0;
     const uint64_t per = (uint64_t(1) << n) / nchunks;
-    double acc[2] = {0.0, 0.0};
+    double acc[2 * kPauliRow];
+#pragma unroll
+    for (int j = 0; j < 2 * kPauliRow; j++) acc[j] = 0.0;
     for (uint64_t x = uint64_t(chunk) * per + threadIdx.x; x < uint64_t(chunk + 1) * per; x += NT) {
         const Cx<T> a = st[x], c = st[x ^ xm];
         const double ar = double(a.re), ai = double(a.im), cr = double(c.re), ci = double(c.im);
         // conj(c) * a
-        double re = cr * ar + ci * ai, im = cr * ai - ci * ar;
-        if (__builtin_popcountll(x & zm) & 1) { re = -re; im = -im; }
-        acc[0] += re;
-        acc[1] += im;
+        const double re = cr * ar + ci * ai, im = cr * ai - ci * ar;
+#pragma unroll
+        for (int j = 0; j < kPauliRow; j++) {
+            if (j < cnt) {
+                const bool odd = __builtin_popcountll(x & z[j]) & 1;
+                acc[2 * j] += odd ? -re : re;
+                acc[2 * j + 1] += odd ? -im : im;
+            }
+        }
     }
-    block_sum<2>(acc);
+    block_sum<2 * kPauliRow>(acc);
     if (threadIdx.x == 0) {
-        const size_t o = (size_t(blockIdx.z) * gridDim.y + k) * 2;
-        partials[(o + 0) * nchunks + chunk] = acc[0];
-        partials[(o + 1) * nchunks + chunk] = acc[1];
+        for (int j = 0; j < cnt; j++) {
+            const size_t o = (size_t(blockIdx.z) * nterms + size_t(row[2 + j])) * 2;
+            partials[(o + 0) * nchunks + chunk] = acc[2 * j];
+            partials[(o + 1) * nchunks + chunk] = acc[2 * j + 1];
+        }
     }
 }
 
@@ -1619,17 +1640,40 @@ uint32_t pauli_chunks(int n) {
     return uint32_t(c);
 }
 
+uint32_t pauli_rows(const qsim_pauli *t, size_t nt, std::vector<uint64_t> *table) {
+    std::vector<uint32_t> idx(nt);
+    for (size_t k = 0; k < nt; k++) idx[k] = uint32_t(k);
+    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) { return t[a].xmask < t[b].xmask; });
+    table->assign(nt, 0);
+    for (size_t k = 0; k < nt; k++) (*table)[k] = t[k].zmask;
+    uint32_t rows = 0;
+    for (size_t i = 0; i < nt;) {
+        size_t j = i;
+        while (j < nt && j - i < size_t(kPauliRow) && t[idx[j]].xmask == t[idx[i]].xmask) j++;
+        table->push_back(t[idx[i]].xmask);
+        table->push_back(uint64_t(j - i));
+        for (int s = 0; s < kPauliRow; s++) table->push_back(i + s < j ? idx[i + s] : 0);
+        rows++;
+        i = j;
+    }
+    return rows;
+}
+
 int launch_pauli(int dtype, const void *state, uint64_t sstride, uint32_t nstates, int n,
-                 const uint64_t *xmask, const uint64_t *zmask, int nterms, double *partials,
+                 const uint64_t *table, int nterms, uint32_t nrows, double *partials,
                  double *out, hipStream_t st, uint32_t nchunks_override) {
     if (nterms <= 0) return QSIM_OK;
+    if (nrows == 0 || nrows > uint32_t(nterms)) return QSIM_E_ARG;
     uint32_t nchunks = pauli_chunks(n);
     if (nchunks_override && nchunks_override < nchunks) nchunks = nchunks_override;
-    const dim3 grid(nchunks, uint32_t(nterms), nstates);
+    const dim3 grid(nchunks, nrows, nstates);
+    const uint64_t *rows = table + nterms;
     if (dtype == QSIM_C64)
-        hipLaunchKernelGGL(k_pauli<float>, grid, dim3(NT), 0, st, (const Cx<float> *)state, sstride, n, xmask, zmask, partials);
+        hipLaunchKernelGGL(k_pauli<float>, grid, dim3(NT), 0, st, (const Cx<float> *)state, sstride, n, table, rows,
+                           uint32_t(nterms), partials);
     else
-        hipLaunchKernelGGL(k_pauli<double>, grid, dim3(NT), 0, st, (const Cx<double> *)state, sstride, n, xmask, zmask, partials);
+        hipLaunchKernelGGL(k_pauli<double>, grid, dim3(NT), 0, st, (const Cx<double> *)state, sstride, n, table, rows,
+                           uint32_t(nterms), partials);
     hipLaunchKernelGGL(k_finish, dim3(uint32_t(nstates) * uint32_t(nterms) * 2), dim3(NT), 0, st,
                        partials, nchunks, out);
     return check(hipGetLastError());

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "host.h"
 
@@ -156,10 +157,14 @@ int launch_probs_noalloc(int dtype, const void *state, int n, const int *qs, int
                          hipStream_t st);
 
 // Pauli-term overlaps S_k = sum_x (-1)^{popcount(x & z_k)} conj(a[x ^ x_k]) a[x]
-// (complex, FP64) for terms on device (masks arrays), written as
-// out[(b * nterms + k) * 2 + {0,1}].
+// (complex, FP64), written as out[(b * nterms + k) * 2 + {0,1}].  Terms that
+// share an X mask share one read of the state: pauli_rows builds the device
+// table (the zmask of every term, then rows of up to kPauliRow terms with a
+// common X mask: xmask, count, term indices) and returns the row count.
+constexpr int kPauliRow = 8;
+uint32_t pauli_rows(const qsim_pauli *t, size_t nt, std::vector<uint64_t> *table);
 int launch_pauli(int dtype, const void *state, uint64_t sstride, uint32_t nstates, int n,
-                 const uint64_t *xmask, const uint64_t *zmask, int nterms, double *partials,
+                 const uint64_t *table, int nterms, uint32_t nrows, double *partials,
                  double *out, hipStream_t st, uint32_t nchunks = 0);
 uint32_t pauli_chunks(int n);
 

@@ -156,6 +156,7 @@ const std::unordered_map<std::string, Builtin> &builtins() {
         {"cu3", {QSIM_G_CU3, 3, 2}},    {"rxx", {QSIM_G_RXX, 1, 2}},   {"rzz", {QSIM_G_RZZ, 1, 2}},
         {"ccx", {QSIM_G_CCX, 0, 3}},    {"cswap", {QSIM_G_CSWAP, 0, 3}}, {"c3x", {QSIM_G_C3X, 0, 4}},
         {"c3sqrtx", {QSIM_G_C3XSQRTX, 0, 4}}, {"c4x", {QSIM_G_C4X, 0, 5}},
+        {"rccx", {QSIM_G_RCCX, 0, 3}},  {"rc3x", {QSIM_G_RC3X, 0, 4}},
     };
     return b;
 }

@@ -52,6 +52,11 @@ int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const GateI
                     bool keep_params, bool allow_meas, int max_params,
                     const qsim_fuse_opts *opt, Compiled *out);
 int validate_plan(int n, int dtype, const Compiled &c);
+// Time fusion widths 2..5 (complex128: 2..4) for this circuit on a scratch
+// state of width n (allocated and freed here), each compiled with `base`
+// otherwise; writes the fastest width and its time per input gate.
+int tune_width(int n, int dtype, const qsim_gate *g, size_t ng, const GateInputs &in,
+               const qsim_fuse_opts *base, int *best_w, double *best_ns);
 int upload_plan(DeviceTables *dt, int dtype, const PackedPlan &plan, hipStream_t st);
 void free_tables(DeviceTables *dt);
 int enqueue_passes(const Compiled &c, const DeviceTables &dt, int dtype, void *state,

@@ -112,6 +112,7 @@ struct Slot {
 
 int grow_dev(void **p, size_t *cap, size_t need) {
     if (need <= *cap) return QSIM_OK;
+    if (alloc_fault()) return QSIM_E_NOMEM;
     if (*p) (void)hipFree(*p);
     *p = nullptr;
     *cap = 0;
@@ -124,6 +125,7 @@ int grow_dev(void **p, size_t *cap, size_t need) {
 
 int grow_pinned(void **p, size_t *cap, size_t need) {
     if (need <= *cap) return QSIM_OK;
+    if (alloc_fault()) return QSIM_E_NOMEM;
     if (*p) (void)hipHostFree(*p);
     *p = nullptr;
     *cap = 0;
@@ -225,13 +227,13 @@ int launch_request(qsim_server *s, Slot &sl, Request *r) {
     if ((rc = grow_pinned((void **)&sl.h_out, &sl.cap_out, (1 + 2 * nt) * 8))) return rc;
     if ((rc = qk::launch_marginal(dtype, state, 0, 1, r->n, nullptr, 0, d_part, d_out, sl.st))) return rc;
     if (nt) {
-        if ((rc = grow_dev((void **)&sl.d_masks, &sl.cap_masks, 16 * nt))) return rc;
-        std::vector<uint64_t> m(2 * nt);
-        for (size_t k = 0; k < nt; k++) { m[k] = r->terms[k].xmask; m[nt + k] = r->terms[k].zmask; }
+        std::vector<uint64_t> m;
+        const uint32_t nrows = qk::pauli_rows(r->terms.data(), nt, &m);
+        if ((rc = grow_dev((void **)&sl.d_masks, &sl.cap_masks, 8 * m.size()))) return rc;
         // synchronous copy: the slot's previous request has completed
-        if ((rc = qk::note_hip(hipMemcpy(sl.d_masks, m.data(), 16 * nt, hipMemcpyHostToDevice), "masks"))) return rc;
-        if ((rc = qk::launch_pauli(dtype, state, 0, 1, r->n, sl.d_masks, sl.d_masks + nt, int(nt), d_part,
-                                   d_out + 1, sl.st)))
+        if ((rc = qk::note_hip(hipMemcpy(sl.d_masks, m.data(), 8 * m.size(), hipMemcpyHostToDevice), "masks")))
+            return rc;
+        if ((rc = qk::launch_pauli(dtype, state, 0, 1, r->n, sl.d_masks, int(nt), nrows, d_part, d_out + 1, sl.st)))
             return rc;
     }
     if ((rc = qk::note_hip(hipMemcpyAsync(sl.h_out, d_out, (1 + 2 * nt) * 8, hipMemcpyDeviceToHost, sl.st),
@@ -302,6 +304,7 @@ void scheduler_loop(qsim_server *s) {
                     if (!s->alloc->alloc(q->bytes, &q->off)) break;
                     s->waiting.erase(it);
                     s->st.in_flight++;
+                    s->st.peak_in_flight = std::max(s->st.peak_in_flight, s->st.in_flight);
                     r = q;
                     break;
                 }

@@ -72,6 +72,7 @@ def _load():
     P, I, SZ, D = C.c_void_p, C.c_int, C.c_size_t, C.c_double
     sig = {
         "qsim_version": ([], I),
+        "qsim_debug_fail_alloc": ([I], I),
         "qsim_strerror": ([I], C.c_char_p),
         "qsim_last_error": ([], C.c_char_p),
         "qsim_create": ([I, I, P, SZ, P, P], I),
@@ -108,6 +109,7 @@ def _load():
         "qsim_batch_results": ([P, I, P, P, P, P, P], I),
         "qsim_batch_get_state": ([P, I, I, P], I),
         "qsim_batch_info_get": ([P, P], I),
+        "qsim_batch_group_stats": ([P, I, P, P], I),
         "qsim_batch_destroy": ([P], I),
     }
     for name, (args, res) in sig.items():
@@ -144,13 +146,13 @@ class qsim_batch_group(C.Structure):
 
 class qsim_batch_opts(C.Structure):
     _fields_ = [("dtype", C.c_int32), ("use_graph", C.c_int32), ("max_params", C.c_int32),
-                ("pad", C.c_int32), ("fuse", qsim_fuse_opts)]
+                ("autotune", C.c_int32), ("fuse", qsim_fuse_opts)]
 
 
 class qsim_batch_info(C.Structure):
     _fields_ = [("states", C.c_int64), ("input_gates", C.c_int64), ("fused_ops", C.c_int64),
                 ("passes", C.c_int64), ("state_bytes", C.c_int64), ("coef_bytes", C.c_int64),
-                ("compile_seconds", C.c_double)]
+                ("compile_seconds", C.c_double), ("tune_seconds", C.c_double)]
 
 
 _lib = _load()
@@ -363,7 +365,7 @@ class Batch:
     tensor of n_states * 2^n elements to run in place)."""
 
     def __init__(self, groups, dtype="complex64", use_graph=False, max_params=0,
-                 level=None, max_width=None, tile_qubits=None, flags=0):
+                 level=None, max_width=None, tile_qubits=None, flags=0, autotune=False):
         self.dtype = QSIM_DTYPES[dtype]
         self._keep = []
         arr = (qsim_batch_group * len(groups))()
@@ -404,6 +406,7 @@ class Batch:
         o.dtype = self.dtype
         o.use_graph = int(bool(use_graph))
         o.max_params = int(max_params)
+        o.autotune = int(bool(autotune))
         fo = _opts(level, max_width, tile_qubits, flags)
         if fo is not None:
             o.fuse = fo
@@ -440,6 +443,14 @@ class Batch:
         check(_lib.qsim_batch_info_get(self.h, C.byref(i)))
         return {f: getattr(i, f) for f, _ in qsim_batch_info._fields_}
 
+    def qsim_batch_group_stats(self, group: int) -> dict:
+        s = qsim_apply_stats()
+        w = C.c_int32()
+        check(_lib.qsim_batch_group_stats(self.h, int(group), C.byref(s), C.byref(w)), "qsim_batch_group_stats")
+        d = s.as_dict()
+        d["tuned_width"] = w.value
+        return d
+
     def close(self):
         if getattr(self, "h", None):
             _lib.qsim_batch_destroy(self.h)
@@ -472,7 +483,7 @@ class qsim_result(C.Structure):
 class qsim_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
                 ("in_flight", C.c_int64), ("waiting", C.c_int64), ("pool_bytes", C.c_size_t),
-                ("pool_in_use", C.c_size_t), ("pool_peak", C.c_size_t)]
+                ("pool_in_use", C.c_size_t), ("pool_peak", C.c_size_t), ("peak_in_flight", C.c_int64)]
 
 
 class Server:
@@ -653,3 +664,9 @@ def qsim_stream_copy(dst, src, flags=0, rotate=0, stream=None):
     st = stream if stream is not None else torch.cuda.current_stream(src.device)
     check(_lib.qsim_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes, int(flags),
                                 int(rotate) & 0xffffffff, C.c_void_p(st.cuda_stream)), "qsim_stream_copy")
+
+
+def qsim_debug_fail_alloc(after: int):
+    """Make the library's allocation attempt `after` attempts from now fail
+    once (QSIM_E_NOMEM); -1 disarms."""
+    check(_lib.qsim_debug_fail_alloc(int(after)), "qsim_debug_fail_alloc")

@@ -159,3 +159,35 @@ def test_alone_equals_in_batch_and_graph_replays(Q):
             first = many.qsim_batch_results(0)["norms"]
         else:
             assert np.array_equal(many.qsim_batch_results(0)["norms"], first)
+
+
+def test_autotuned_batch_uses_tuned_width(Q):
+    """With autotune, each group's fusion width is timed (2..5 for complex64)
+    on its template with the first state's angles, and the group is compiled
+    with the fastest; results still match the oracle."""
+    groups, want = [], []
+    for w in (11, 16):
+        rng = np.random.default_rng(100 + w)
+        strings = W.pauli_strings(w, 60, rng)
+        recs = []
+        for e, (qs, letters) in enumerate(strings):
+            W.compile_pauli_exponential(qs, letters, 0.0, e, recs)
+        g = W.gates(recs)
+        H = W.pauli_sum(w, 20, seed=w)
+        th = rng.normal(0, 0.4, size=(3, 60))
+        groups.append({"n": w, "n_states": 3, "gates": g, "params": th, "terms": H})
+        want.append((w, g, H, th))
+    say("autotuned batch")
+    b = Q.Batch(groups, dtype="complex64", autotune=True)
+    info = b.qsim_batch_info()
+    assert info["tune_seconds"] > 0
+    b.qsim_batch_run()
+    for gi, (w, g, H, th) in enumerate(want):
+        st = b.qsim_batch_group_stats(gi)
+        assert 2 <= st["tuned_width"] <= 5 and st["max_width"] == st["tuned_width"]
+        res = b.qsim_batch_results(gi)
+        for s in range(3):
+            psi, _, _ = oracle.run(w, g, params=th[s])
+            assert oracle.infidelity(psi, b.qsim_batch_get_state(gi, s)) < 1e-5
+            assert abs(res["expvals"][s] - oracle.expval(w, psi, H)) <= 1e-6 * np.abs(H["coeff"]).sum()
+    b.close()

@@ -112,3 +112,31 @@ def test_largest_state_sampled_amplitudes(Q, dtype, n):
     got2 = sv.tensor[torch.as_tensor(xs, device=sv.tensor.device)].cpu().numpy().astype(np.complex128)
     assert np.abs(got2 - want).max() <= (1e-10 if dtype == "complex128" else 1e-3) * scale
     sv.close()
+
+
+def test_out_of_memory_leaves_state_unchanged(Q):
+    """qsim_apply failing on any of its allocations (the compile, the pinned
+    staging buffer, the device tables) returns QSIM_E_NOMEM and leaves the
+    state as it was; the next call works."""
+    n = 12
+    g1, _, _ = W.pauli_exponential_circuit(n, 30, seed=1)
+    g2, _, _ = W.pauli_exponential_circuit(n, 60, seed=2)
+    for after in range(4):
+        print("out of memory at allocation", after, flush=True)
+        sv = Q.StateVector(n, "complex128")
+        sv.qsim_apply(g1[:5])
+        before = sv.qsim_get_state()
+        Q.qsim_debug_fail_alloc(after)
+        try:
+            sv.qsim_apply(g2)
+            failed = False
+        except Q.QsimError as e:
+            assert e.code == Q.E_NOMEM
+            failed = True
+        Q.qsim_debug_fail_alloc(-1)
+        if failed:
+            assert np.array_equal(sv.qsim_get_state(), before)
+        sv.qsim_apply(g1)
+        want, _, _ = oracle.run(n, np.concatenate([g1[:5]] + ([] if failed else [g2]) + [g1]))
+        assert oracle.infidelity(want, sv.qsim_get_state()) < 1e-12
+        sv.close()

@@ -191,6 +191,33 @@ def test_probs_norm_expval(Q, dtype):
     assert abs(sv.qsim_expval(H) - oracle.expval(n, psi, H)) <= 1e-6 * np.abs(H["coeff"]).sum()
 
 
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+def test_expval_terms_sharing_x_masks(Q, dtype):
+    """Terms with a common X mask share one read of the state (rows of up to
+    8 terms): all-Z terms, 11 terms on one X mask (two rows), and singles,
+    in scrambled order; each term and the sum against the oracle."""
+    n = 16
+    g, _, _ = W.pauli_exponential_circuit(n, 150, seed=31)
+    sv = run_gpu(Q, n, g, dtype)
+    psi, _, _ = oracle.run(n, g)
+    rng = np.random.default_rng(8)
+    terms = []
+    for i in range(n):
+        terms.append((rng.normal(), 0, 1 << i))
+    xm = (1 << 3) | (1 << 9) | (1 << 14)
+    for j in range(11):
+        terms.append((rng.normal(), xm, int(rng.integers(0, 1 << n))))
+    H0 = W.pauli_sum(n, 12, seed=5)
+    for t in H0:
+        terms.append((float(t["coeff"]), int(t["xmask"]), int(t["zmask"])))
+    order = rng.permutation(len(terms))
+    H = np.array([terms[i] for i in order], dtype=W.PAULI_DTYPE)
+    tol = 1e-6 * np.abs(H["coeff"]).sum()
+    assert abs(sv.qsim_expval(H) - oracle.expval(n, psi, H)) <= tol
+    for k in range(0, len(H), 7):
+        assert abs(sv.qsim_expval(H[k:k + 1]) - oracle.expval(n, psi, H[k:k + 1])) <= 1e-6 * abs(H["coeff"][k])
+
+
 def test_deterministic_repeat(Q):
     n = 20
     g, _, _ = W.pauli_exponential_circuit(n, 300, seed=12)

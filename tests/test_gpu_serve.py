@@ -78,6 +78,11 @@ def test_alone_equals_in_mix(Q):
     m = got[ids[7]]
     assert np.array_equal(m["state"], a["state"])
     assert m["expval"] == a["expval"] and m["norm"] == a["norm"]
+    # the probe shared the device: its admit..done interval overlaps another
+    # request's, and several requests were resident at once
+    overlaps = [i for i in ids if i != ids[7] and got[i]["t_admit"] < m["t_done"] and m["t_admit"] < got[i]["t_done"]]
+    assert overlaps, "the probe ran alone in the mix"
+    assert mix.qsim_server_stats()["peak_in_flight"] > 1
     mix.close()
 
 

@@ -222,3 +222,19 @@ def test_one_hip_runtime_after_import():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr[-2000:]
     assert out.stdout.split()[0] == "1", out.stdout
+
+
+def test_allocation_failure_reports_nomem_once():
+    """The allocation-failure hook makes the next compile report
+    QSIM_E_NOMEM; the call after it succeeds and gives the same plan."""
+    g = W.random_circuit(8, 120, seed=4)
+    ok = qsim.qsim_debug_plan(8, g)
+    for call in (lambda: qsim.qsim_debug_plan(8, g), lambda: qsim.qsim_debug_emulate(8, g),
+                 lambda: qsim.qsim_debug_fuse(8, g)):
+        qsim.qsim_debug_fail_alloc(0)
+        with pytest.raises(qsim.QsimError) as e:
+            call()
+        assert e.value.code == qsim.E_NOMEM
+    again = qsim.qsim_debug_plan(8, g)
+    assert again["passes"] == ok["passes"] and again["fused_ops"] == ok["fused_ops"]
+    qsim.qsim_debug_fail_alloc(-1)

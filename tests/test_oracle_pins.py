@@ -193,6 +193,53 @@ def test_c3sqrtx_squares_to_c3x():
     np.testing.assert_allclose(a @ a, mat_of(W.KIND_C3X, 4), atol=1e-15)
 
 
+def _local_op(k, u, bit):
+    """k-bit operator applying the 2x2 u to local bit `bit` (bit 0 least
+    significant), as an explicit Kronecker product."""
+    ops = [np.eye(2)] * k
+    ops[bit] = u
+    out = np.eye(1)
+    for o in reversed(ops):
+        out = np.kron(out, o)
+    return out
+
+
+def _local_cx(k, c, t):
+    d = 1 << k
+    m = np.zeros((d, d))
+    for x in range(d):
+        m[x ^ (1 << t) if (x >> c) & 1 else x, x] = 1
+    return m
+
+
+@pytest.mark.parametrize("kind,base,seq", [
+    (W.KIND_RCCX, W.KIND_CCX, [("h", 2), ("t", 2), ("cx", 1), ("tdg", 2), ("cx", 0), ("t", 2), ("cx", 1),
+                               ("tdg", 2), ("h", 2)]),
+    (W.KIND_RC3X, W.KIND_C3X, [("h", 3), ("t", 3), ("cx", 2), ("tdg", 3), ("h", 3), ("cx", 0), ("t", 3),
+                               ("cx", 1), ("tdg", 3), ("cx", 0), ("t", 3), ("cx", 1), ("tdg", 3), ("h", 3),
+                               ("t", 3), ("cx", 2), ("tdg", 3), ("h", 3)])])
+def test_relative_phase_toffolis(kind, base, seq):
+    """RCCX and RC3X (OpenQASM's rccx, rc3x): the product of their standard
+    gate sequences, built here from Kronecker products of H, T and CNOT, and
+    equal to CCX / C3X up to a diagonal of unit-modulus phases."""
+    k = W.KIND_QUBITS[kind]
+    H = np.array([[1, 1], [1, -1]]) / math.sqrt(2)
+    T = np.diag([1, np.exp(0.25j * math.pi)])
+    want = np.eye(1 << k, dtype=complex)
+    for name, q in seq:
+        if name == "cx":
+            g = _local_cx(k, q, k - 1)
+        else:
+            g = _local_op(k, {"h": H, "t": T, "tdg": T.conj().T}[name], q)
+        want = g @ want
+    got = mat_of(kind, k)
+    np.testing.assert_allclose(got, want, atol=1e-15)
+    d = got @ mat_of(base, k).conj().T
+    np.testing.assert_allclose(d, np.diag(np.diag(d)), atol=1e-15)
+    np.testing.assert_allclose(np.abs(np.diag(d)), 1.0, atol=1e-15)
+    assert not np.allclose(np.diag(d), 1.0)     # a genuine relative phase
+
+
 def test_sx_branch_is_h_s_h():
     """SX is the square root of X with eigenvalues (1, i) on (|+>, |->): the
     conjugation of S by H.  Squaring alone admits four roots of X; this fixes

@@ -91,7 +91,7 @@ cz a, b[1:0];
     ("OPENQASM 2.0;\nqreg q[2];\nh q[0]\ncx q[0], q[1];\n", "E_ARG", 4),            # missing ';'
     ("OPENQASM 2.0;\nqreg q[2];\ncreg c[1];\nif (c==1) x q[0];\n", "E_UNSUPPORTED", 4),
     ("OPENQASM 2.0;\nqreg q[2];\nopaque g a;\n", "E_UNSUPPORTED", 3),
-    ("OPENQASM 2.0;\nqreg q[2];\nrccx q[0], q[1], q[0];\n", "E_UNSUPPORTED", 3),   # not lowered
+    ("OPENQASM 2.0;\nqreg q[2];\nrccx q[0], q[1], q[0];\n", "E_QUBIT", 3),         # repeated qubit
     ("OPENQASM 2.0;\nqreg q[2];\nrx q[0];\n", "E_ARG", 3),                          # missing angle
     ("OPENQASM 2.0;\nqreg q[2];\nx q[2];\n", "E_QUBIT", 3),
     ("OPENQASM 2.0;\nqreg q[2];\ncx q[1], q[1];\n", "E_QUBIT", 3),

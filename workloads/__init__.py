@@ -42,6 +42,7 @@ KIND_CX, KIND_CY, KIND_CZ, KIND_CH, KIND_SWAP = 20, 21, 22, 23, 24
 KIND_CRX, KIND_CRY, KIND_CRZ, KIND_CU1, KIND_CU3 = 25, 26, 27, 28, 29
 KIND_RXX, KIND_RZZ = 30, 31
 KIND_CCX, KIND_CSWAP, KIND_C3X, KIND_C3XSQRTX, KIND_C4X = 40, 41, 44, 45, 46
+KIND_RCCX, KIND_RC3X = 42, 43
 KIND_MAT = 50
 KIND_BARRIER, KIND_MEASURE, KIND_RESET, KIND_ASSERT0 = 60, 61, 62, 63
 
@@ -53,7 +54,7 @@ KIND_NAMES = {
     KIND_SWAP: "swap", KIND_CRX: "crx", KIND_CRY: "cry", KIND_CRZ: "crz",
     KIND_CU1: "cu1", KIND_CU3: "cu3", KIND_RXX: "rxx", KIND_RZZ: "rzz",
     KIND_CCX: "ccx", KIND_CSWAP: "cswap", KIND_C3X: "c3x",
-    KIND_C3XSQRTX: "c3sqrtx", KIND_C4X: "c4x", KIND_MAT: "mat",
+    KIND_C3XSQRTX: "c3sqrtx", KIND_C4X: "c4x", KIND_RCCX: "rccx", KIND_RC3X: "rc3x", KIND_MAT: "mat",
     KIND_BARRIER: "barrier", KIND_MEASURE: "measure", KIND_RESET: "reset",
     KIND_ASSERT0: "assert0",
 }
@@ -64,7 +65,7 @@ KIND_QUBITS = {
     KIND_CZ: 2, KIND_CH: 2, KIND_SWAP: 2, KIND_CRX: 2, KIND_CRY: 2,
     KIND_CRZ: 2, KIND_CU1: 2, KIND_CU3: 2, KIND_RXX: 2, KIND_RZZ: 2,
     KIND_CCX: 3, KIND_CSWAP: 3, KIND_C3X: 4, KIND_C3XSQRTX: 4, KIND_C4X: 5,
-    KIND_MEASURE: 1, KIND_RESET: 1, KIND_ASSERT0: 1,
+    KIND_RCCX: 3, KIND_RC3X: 4, KIND_MEASURE: 1, KIND_RESET: 1, KIND_ASSERT0: 1,
 }
 KIND_NPARAMS = {KIND_RX: 1, KIND_RY: 1, KIND_RZ: 1, KIND_U1: 1, KIND_U2: 2,
                 KIND_U3: 3, KIND_CRX: 1, KIND_CRY: 1, KIND_CRZ: 1,
@@ -418,6 +419,7 @@ QASM_NAMES = {
     KIND_CH: "ch", KIND_SWAP: "swap", KIND_CRX: "crx", KIND_CRY: "cry", KIND_CRZ: "crz",
     KIND_CU1: "cu1", KIND_CU3: "cu3", KIND_RXX: "rxx", KIND_RZZ: "rzz", KIND_CCX: "ccx",
     KIND_CSWAP: "cswap", KIND_C3X: "c3x", KIND_C3XSQRTX: "c3sqrtx", KIND_C4X: "c4x",
+    KIND_RCCX: "rccx", KIND_RC3X: "rc3x",
 }
 
 
