@@ -469,6 +469,9 @@ def main():
     ap.add_argument("--dtype", default="complex128", choices=["complex128", "complex64"])
     ap.add_argument("--qubits", type=int, default=21)
     ap.add_argument("--n-exp", type=int, default=50_000)
+    ap.add_argument("--workload", default="pauli", choices=["pauli", "dense"],
+                    help="pauli: the Pauli-exponential circuit; dense: brick-wall layers of Haar-random "
+                         "two-qubit unitaries (--n-exp sets the number of layers)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the passes as a HIP graph")
     ap.add_argument("--only", action="store_true", help="skip the other dtype")
@@ -502,14 +505,19 @@ def main():
         del src, dst
 
     n = args.qubits
-    log(f"[bench] generating circuit: {n} qubits, {args.n_exp} exponentials")
-    g, _, _ = W.pauli_exponential_circuit(n, args.n_exp, seed=2)
+    mats = None
+    if args.workload == "dense":
+        log(f"[bench] generating circuit: {n} qubits, {args.n_exp} dense brick-wall layers")
+        g, mats = W.dense_brickwork_circuit(n, args.n_exp, seed=41)
+    else:
+        log(f"[bench] generating circuit: {n} qubits, {args.n_exp} exponentials")
+        g, _, _ = W.pauli_exponential_circuit(n, args.n_exp, seed=2)
     H = W.pauli_sum(n, 100, seed=3)
 
     def measure(dtype):
         log(f"[bench] compile {dtype}")
         t0 = time.perf_counter()
-        prog = qsim.Program(n, g, dtype)
+        prog = qsim.Program(n, g, dtype, mats=mats)
         compile_s = time.perf_counter() - t0
         st = prog.qsim_program_stats()
         sv = qsim.StateVector(n, dtype)
@@ -544,7 +552,7 @@ def main():
                "compile_s": compile_s, "stats": st, "energy": energy, "norm": sv.qsim_norm()}
         # a circuit run once: host compile (fusion + plan) plus one device run
         res["gates_per_s_with_compile"] = st["input_gates"] / (compile_s + dt / args.steps)
-        if n == 21 and args.n_exp == 50_000 and os.path.exists(FIXTURE):
+        if n == 21 and args.n_exp == 50_000 and args.workload == "pauli" and os.path.exists(FIXTURE):
             log(f"[bench] {dtype}: final state against the oracle's stored results")
             res["vs_oracle"] = oracle_distance(W, sv.qsim_get_state(), energy, H)
         if not args.graph:

@@ -78,6 +78,7 @@ void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc
     pc->first_in_regs = env_int("QSIM_FIRST_IN_REGS", 1) != 0;
     pc->reg_engine = env_int("QSIM_REG_ENGINE", 0) != 0;
     pc->reg_coalesce = env_int("QSIM_REG_COALESCE", 1) != 0;
+    pc->xcd_order = env_int("QSIM_XCD_ORDER", 1) != 0;
     if (opt) {
         if (opt->level >= 0 && opt->level <= 5) fc->level = opt->level;
         if (opt->max_width > 0) fc->max_width = opt->max_width;
@@ -107,6 +108,17 @@ void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc
     pc->meta_budget = std::min(room, size_t(std::max(1024, env_int("QSIM_META_BUDGET", 16 * 1024))));
 }
 
+// The XCD-order qubits of a tiled pass: distinct qubits outside the tile.
+bool xcd_ok(uint64_t rest, int nx, const uint8_t *xq) {
+    if (nx < 0 || nx > 3 || nx > __builtin_popcountll(rest)) return false;
+    uint64_t seen = 0;
+    for (int j = 0; j < nx; j++) {
+        if (xq[j] >= 64 || !((rest >> xq[j]) & 1) || ((seen >> xq[j]) & 1)) return false;
+        seen |= uint64_t(1) << xq[j];
+    }
+    return true;
+}
+
 // A register-resident pass: tile qubits partition the n qubits, layouts are
 // permutations of the tile positions, every record is well formed, the
 // re-layout records name the layout the swaps and re-layouts before them
@@ -134,6 +146,7 @@ int validate_reg_pass(int n, int dtype, const Compiled &c, size_t i) {
         tile |= uint64_t(1) << ra.tq[j];
     }
     if ((tile & ra.rest_mask) || ((tile | ra.rest_mask) != all)) return QSIM_E_ARG;
+    if (!xcd_ok(ra.rest_mask, ra.nxcd, ra.xcd_q)) return QSIM_E_ARG;
     auto is_perm = [&](const uint8_t *pos) {
         uint32_t seen = 0;
         for (int x = 0; x < t; x++) {
@@ -213,6 +226,7 @@ int validate_plan(int n, int dtype, const Compiled &c) {
                 m |= uint64_t(1) << ta.hi[h];
             }
             if ((m & ta.rest_mask) || ((m | ta.rest_mask) != all) || m != ta.tile_mask) return QSIM_E_ARG;
+            if (!xcd_ok(ta.rest_mask, ta.nxcd, ta.xcd_q)) return QSIM_E_ARG;
             // tile positions: the low qubits first, then every other tile
             // qubit once
             uint64_t mq = 0;
@@ -320,6 +334,7 @@ int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const GateI
         p.reg = pc.reg_engine && p.kind == Pass::TILE && !p.strided && p.t < n && reg_threads_for(p.t) > 0 &&
                 p.c <= 4 && p.inline_meas.empty();
     place_positions(n, L.ops, pc.threads == 512 ? 9 : 8, first_regs_max_k(dtype), pc.first_in_regs, &passes);
+    if (pc.xcd_order) place_xcd_qubits(n, &passes);
     rc = pack_plan(L.ops, present, passes, pc, &out->plan);
     if (rc) return rc;
     // LDS slot offsets of the tile positions (the tile kernel's layout)
@@ -349,7 +364,11 @@ int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const GateI
         pi.ta.regs = (p.first_in_regs ? 1 : 0) | (p.last_in_regs ? 2 : 0) | (p.last_off << 2);
         for (int h = 0; h < p.nhi; h++) pi.ta.hi[h] = uint8_t(p.hi[h]);
         for (int j = 0; j < 16; j++) pi.ta.tq[j] = p.tq[j];
+        pi.ta.nxcd = p.nxcd;
+        for (int j = 0; j < 4; j++) pi.ta.xcd_q[j] = p.xcd_q[j];
         if (p.reg) {
+            pi.ra.nxcd = p.nxcd;
+            for (int j = 0; j < 4; j++) pi.ra.xcd_q[j] = p.xcd_q[j];
             pi.reg = true;
             pi.ra.rest_mask = pi.ta.rest_mask;
             pi.ra.n = n;
@@ -1250,12 +1269,7 @@ int qsim_debug_emulate(int n, int dtype, const qsim_gate *g, size_t ng, const do
             const int t = ra.t, logt = t - kRegBits;
             std::vector<cd> v(size_t(1) << t), w(v.size());
             for (uint64_t tile = 0; tile < (uint64_t(1) << (n - t)); tile++) {
-                uint64_t base = 0, bits = tile;
-                for (int q = 0; q < n; q++)
-                    if ((ra.rest_mask >> q) & 1) {
-                        if (bits & 1) base |= uint64_t(1) << q;
-                        bits >>= 1;
-                    }
+                const uint64_t base = qk::tile_base(tile, ra.rest_mask, ra.nxcd, ra.xcd_q);
                 auto addr = [&](uint64_t P, const uint8_t *pos) {
                     uint64_t a = base;
                     for (int b = 0; b < t; b++)
@@ -1321,13 +1335,8 @@ int qsim_debug_emulate(int n, int dtype, const qsim_gate *g, size_t ng, const do
         const int t = ta.t;
         std::vector<cd> v(size_t(1) << t);
         for (uint64_t tile = 0; tile < (uint64_t(1) << (n - t)); tile++) {
-            // the tile index deposited into the qubits outside the tile
-            uint64_t base = 0, bits = tile;
-            for (int q = 0; q < n; q++)
-                if ((ta.rest_mask >> q) & 1) {
-                    if (bits & 1) base |= uint64_t(1) << q;
-                    bits >>= 1;
-                }
+            // the workgroup's tile in the kernel's order
+            const uint64_t base = qk::tile_base(tile, ta.rest_mask, ta.nxcd, ta.xcd_q);
             auto addr = [&](uint64_t jpos) {
                 uint64_t a = base;
                 for (int b = 0; b < t; b++)

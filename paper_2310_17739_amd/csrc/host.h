@@ -129,6 +129,8 @@ struct Pass {
     uint8_t load_pos[16] = {0};
     uint8_t store_pos[16] = {0};
     int reg_swaps = 0, reg_xposes = 0;
+    int nxcd = 0;                 // XCD-aware tile order (see qk::TileArgs)
+    uint8_t xcd_q[4] = {0};
 };
 
 struct PlanConfig {
@@ -143,7 +145,13 @@ struct PlanConfig {
     bool first_in_regs = true;    // apply a pass's first operator before the tile reaches LDS
     bool reg_engine = false;      // tiled passes of 10..13 qubits run register-resident
     bool reg_coalesce = true;     // restore the low qubits to lane bits 0..c-1 before the store
+    bool xcd_order = true;        // XCD-aware tile order across passes
 };
+
+// Choose, for every tiled pass, the outside qubits that name a tile's XCD
+// (Pass::xcd_q): those of the previous pass while they stay outside the
+// tile, otherwise the outside qubits that stay outside longest.
+void place_xcd_qubits(int n, std::vector<Pass> *passes);
 
 // Register bits of a register-resident pass: each thread holds 2^kRegBits
 // amplitudes, so a tile of t qubits takes 2^(t - kRegBits) threads.

@@ -602,7 +602,7 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
     // LDS: the tile, the reduction scratch, the pass's records, its coefficients
     const uint32_t rec_at = (uint32_t(sizeof(Cx<T>)) << ta.t) + uint32_t(kTileRedBytes);
     const uint32_t cf_at = rec_at + uint32_t(nrec) * uint32_t(sizeof(DevOp));
-    const uint64_t base = deposit(blockIdx.x, ta.rest_mask);
+    const uint64_t base = tile_base(blockIdx.x, ta.rest_mask, ta.nxcd, ta.xcd_q);
     // thread part: the low log2(TNT) bits of j; iteration part: the bits above
     // (tile position j is qubit ta.tq[j])
     constexpr int LOGT = (TNT == 512) ? 9 : 8;
@@ -865,7 +865,7 @@ __global__ void __launch_bounds__(1 << LOGT) k_reg(Cx<T> *__restrict__ state, ui
     Cx<T> *st = state + size_t(b) * sstride;
     const Cx<T> *cfs = coefs + size_t(b) * cstride;
     const int tid = threadIdx.x;
-    const uint64_t base = deposit(blockIdx.x, ra.rest_mask);
+    const uint64_t base = tile_base(blockIdx.x, ra.rest_mask, ra.nxcd, ra.xcd_q);
     const bool nt = (ra.flags & RF_NONTEMPORAL) != 0;
     typedef uint32_t U4 __attribute__((ext_vector_type(4)));
     const uint32_t nrec = oe - ob;

@@ -30,7 +30,32 @@ struct TileArgs {
                           // last one on the registers stored; bits 2-4: its register-bit offset
     uint8_t tq[16];       // qubit at tile position j
     uint8_t hi[48];
+    // XCD-aware tile order: workgroup b takes the tile whose qubits xcd_q[j]
+    // (outside the tile) equal bit j of b for j < nxcd, the other bits of b
+    // going to the remaining outside qubits in ascending order.  Workgroups
+    // are handed to the XCDs round-robin, so these qubits name the XCD (and
+    // its L2) that processes an amplitude; keeping them from pass to pass
+    // keeps amplitudes in one XCD's L2.
+    int32_t nxcd;
+    uint8_t xcd_q[4];
 };
+
+// Base index of the tile of workgroup bx (see TileArgs::xcd_q).
+__host__ __device__ inline uint64_t tile_base(uint64_t bx, uint64_t rest_mask, int nxcd, const uint8_t *xcd_q) {
+    uint64_t lo = 0, lomask = 0;
+    for (int j = 0; j < nxcd; j++) {
+        lomask |= uint64_t(1) << xcd_q[j];
+        if ((bx >> j) & 1) lo |= uint64_t(1) << xcd_q[j];
+    }
+    uint64_t m = rest_mask & ~lomask, x = bx >> nxcd, r = 0;
+    while (m && x) {
+        const uint64_t low = m & (~m + 1);
+        if (x & 1) r |= low;
+        x >>= 1;
+        m &= m - 1;
+    }
+    return lo | r;
+}
 
 // Measurement inputs / outputs of a batched program (per state b, slot s:
 // index b * nslots + s).
@@ -60,6 +85,8 @@ struct RegArgs {
     uint8_t tq[16];
     uint8_t load_pos[16];
     uint8_t store_pos[16];
+    int32_t nxcd;            // XCD-aware tile order, as in TileArgs
+    uint8_t xcd_q[4];
 };
 enum : uint32_t { RF_NONTEMPORAL = 1 };
 

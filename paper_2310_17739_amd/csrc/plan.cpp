@@ -176,6 +176,60 @@ void plan_passes(int n, const Lowered &L, const std::vector<uint32_t> &meta_byte
     }
 }
 
+void place_xcd_qubits(int n, std::vector<Pass> *passes) {
+    const uint64_t all = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
+    const size_t np = passes->size();
+    // for every qubit, the passes whose tile holds it
+    std::vector<std::vector<int>> in_tile(static_cast<size_t>(n));
+    for (size_t i = 0; i < np; i++) {
+        const Pass &p = (*passes)[i];
+        const bool tiled = p.kind == Pass::TILE && !p.strided;
+        for (int q = 0; q < n; q++)
+            if (!tiled || ((p.tile_mask >> q) & 1)) in_tile[size_t(q)].push_back(int(i));
+    }
+    auto next_in = [&](int q, int after) {
+        const auto &v = in_tile[size_t(q)];
+        auto it = std::upper_bound(v.begin(), v.end(), after);
+        return it == v.end() ? int(np) : *it;
+    };
+    int prev[3] = {-1, -1, -1};
+    for (size_t i = 0; i < np; i++) {
+        Pass &p = (*passes)[i];
+        if (p.kind != Pass::TILE || p.strided || p.tile_mask == all) {
+            prev[0] = prev[1] = prev[2] = -1;
+            continue;
+        }
+        const uint64_t rest = all & ~p.tile_mask;
+        const int nx = std::min(3, __builtin_popcountll(rest));
+        uint64_t used = 0;
+        int cur[3] = {-1, -1, -1};
+        for (int j = 0; j < nx; j++)
+            if (prev[j] >= 0 && ((rest >> prev[j]) & 1)) {
+                cur[j] = prev[j];
+                used |= uint64_t(1) << prev[j];
+            }
+        for (int j = 0; j < nx; j++) {
+            if (cur[j] >= 0) continue;
+            int best = -1, best_next = -1;
+            for (int q = 0; q < n; q++) {
+                if (!((rest >> q) & 1) || ((used >> q) & 1)) continue;
+                const int nx2 = next_in(q, int(i));
+                if (nx2 > best_next) {
+                    best_next = nx2;
+                    best = q;
+                }
+            }
+            cur[j] = best;
+            used |= uint64_t(1) << best;
+        }
+        p.nxcd = nx;
+        for (int j = 0; j < 3; j++) {
+            p.xcd_q[j] = uint8_t(j < nx ? cur[j] : 0);
+            prev[j] = j < nx ? cur[j] : -1;
+        }
+    }
+}
+
 uint32_t op_present(const Op &o, bool sparse) {
     const int d = o.dim();
     if (!sparse) return (d >= 32) ? 0xffffffffu : ((1u << d) - 1);

@@ -405,6 +405,34 @@ def random_complex_matrix(dim: int, seed: int) -> np.ndarray:
     return rng.normal(size=(dim, dim)) + 1j * rng.normal(size=(dim, dim))
 
 
+def random_unitary(dim: int, rng: np.random.Generator) -> np.ndarray:
+    """A Haar-random unitary: QR of a complex Gaussian matrix, with the phases
+    of R's diagonal moved into Q."""
+    z = (rng.normal(size=(dim, dim)) + 1j * rng.normal(size=(dim, dim))) / math.sqrt(2)
+    q, r = np.linalg.qr(z)
+    d = np.diag(r)
+    return q * (d / np.abs(d))
+
+
+def dense_brickwork_circuit(n: int, layers: int, seed: int = 41):
+    """Dense workload: `layers` brick-wall layers of Haar-random two-qubit
+    unitaries (MAT records on (q, q+1), offset alternating between layers).
+    Fusion merges them into dense 4-qubit operators (all 16 XOR shifts
+    present).  Returns (gates, mats)."""
+    rng = _rng(seed, 5)
+    recs, mats = [], []
+    for layer in range(layers):
+        for q in range(layer % 2, n - 1, 2):
+            recs.append((KIND_MAT, (q, q + 1), ()))
+            mats.append(random_unitary(4, rng).ravel())
+    g = gates(recs)
+    off = 0
+    for i in range(len(g)):
+        g[i]["mat_off"] = off
+        off += 16
+    return g, np.concatenate(mats) if mats else np.zeros(0, complex)
+
+
 def random_state(n: int, seed: int) -> np.ndarray:
     """A normalised complex128 state with N(0,1) parts."""
     rng = _rng(seed, 98)
