@@ -469,9 +469,10 @@ def main():
     ap.add_argument("--dtype", default="complex128", choices=["complex128", "complex64"])
     ap.add_argument("--qubits", type=int, default=21)
     ap.add_argument("--n-exp", type=int, default=50_000)
-    ap.add_argument("--workload", default="pauli", choices=["pauli", "dense"],
+    ap.add_argument("--workload", default="pauli", choices=["pauli", "dense", "dense5"],
                     help="pauli: the Pauli-exponential circuit; dense: brick-wall layers of Haar-random "
-                         "two-qubit unitaries (--n-exp sets the number of layers)")
+                         "two-qubit unitaries (--n-exp sets the number of layers); dense5: --n-exp "
+                         "Haar-random 5-qubit unitaries on random qubits")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the passes as a HIP graph")
     ap.add_argument("--only", action="store_true", help="skip the other dtype")
@@ -506,7 +507,10 @@ def main():
 
     n = args.qubits
     mats = None
-    if args.workload == "dense":
+    if args.workload == "dense5":
+        log(f"[bench] generating circuit: {n} qubits, {args.n_exp} dense 5-qubit operators")
+        g, mats = W.dense_operator_circuit(n, args.n_exp, 5, seed=43)
+    elif args.workload == "dense":
         log(f"[bench] generating circuit: {n} qubits, {args.n_exp} dense brick-wall layers")
         g, mats = W.dense_brickwork_circuit(n, args.n_exp, seed=41)
     else:

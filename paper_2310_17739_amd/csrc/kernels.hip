@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <mutex>
 #include <vector>
 
@@ -1011,6 +1012,101 @@ __global__ void __launch_bounds__(NT) k_sweep(Cx<T> *__restrict__ state, uint64_
     }
 }
 
+// ------------------------------------------------- dense MFMA contraction
+// A dense fused operator on KQ = 4 or 5 qubits of a complex64 state, as a
+// real-embedded contraction on the FP32 matrix cores: with M = Mr + i Mi,
+//     [Yr; Yi] = [[Mr, -Mi], [Mi, Mr]] [Xr; Xi]
+// a 2D x 2D real matrix (D = 2^KQ) applied to 32 groups at once by
+// v_mfma_f32_32x32x2f32 (32 x 32 outputs += 32 x 2 times 2 x 32), D steps
+// of two real rows of the group vectors.  Lane l serves group l mod 32 of
+// the wave's 32 and holds its amplitudes 2j + l/32, j < D/2 (the B operand
+// of step s is row 2s + l/32 of [Xr; Xi]); it also holds, for each 32-row
+// block of the real matrix, entry (32 b + l mod 32, 2s + l/32) of step s
+// (the A operand), built once from the operator's XOR-shift diagonals.  The
+// accumulator of 32-row block b holds output row 32 b + 8 (r / 4) +
+// 4 (l / 32) + r mod 4 of group l mod 32 in register r, so every lane ends
+// with the real and imaginary parts of whole output amplitudes.
+typedef float F16v __attribute__((ext_vector_type(16)));
+
+template <int KQ>
+__global__ void __launch_bounds__(NT) k_dense_mfma(Cx<float> *__restrict__ state, uint64_t sstride, int n,
+                                                   DevOp op, const Cx<float> *__restrict__ cf, uint64_t cstride,
+                                                   const int32_t *__restrict__ status) {
+    constexpr int D = 1 << KQ;
+    constexpr int NRB = (2 * D) / 32;
+    constexpr int H = D / 2;
+    if (status && status[blockIdx.y] != 0) return;
+    Cx<float> *st = state + size_t(blockIdx.y) * sstride;
+    const Cx<float> *c = cf + size_t(blockIdx.y) * cstride + op.coef;
+    const int lane = threadIdx.x & 63, nn = lane & 31, kk = lane >> 5;
+    int p[KQ];
+#pragma unroll
+    for (int j = 0; j < KQ; j++) p[j] = op.pos[j];
+    // A operand of every step and row block: real embedding of M[r][col],
+    // M[r][col] = d_m[r] for the XOR shift m = r ^ col when present
+    float a[NRB][D];
+#pragma unroll
+    for (int rb = 0; rb < NRB; rb++) {
+#pragma unroll
+        for (int s = 0; s < D; s++) {
+            const int R = rb * 32 + nn, Cc = 2 * s + kk;
+            const int r = R % D, col = Cc % D;
+            const int m = r ^ col;
+            float re = 0.f, im = 0.f;
+            if ((op.present >> m) & 1u) {
+                const int t = __builtin_popcount(op.present & ((1u << m) - 1u));
+                const Cx<float> v = c[t * D + r];
+                re = v.re;
+                im = v.im;
+            }
+            a[rb][s] = (R < D) ? (Cc < D ? re : -im) : (Cc < D ? im : re);
+        }
+    }
+    auto offset = [&](int r) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int j = 0; j < KQ; j++)
+            if ((r >> j) & 1) o |= uint64_t(1) << p[j];
+        return o;
+    };
+    const uint64_t nblk = (uint64_t(1) << (n - KQ)) / 32;
+    const uint64_t nwaves = uint64_t(gridDim.x) * (NT / 64);
+    for (uint64_t bg = uint64_t(blockIdx.x) * (NT / 64) + (threadIdx.x >> 6); bg < nblk; bg += nwaves) {
+        uint64_t base = bg * 32 + uint64_t(nn);
+#pragma unroll
+        for (int j = 0; j < KQ; j++)
+            base = ((base >> p[j]) << (p[j] + 1)) | (base & ((uint64_t(1) << p[j]) - 1));
+        Cx<float> x[H];
+#pragma unroll
+        for (int j = 0; j < H; j++) x[j] = st[base + offset(2 * j + kk)];
+        F16v acc[NRB];
+#pragma unroll
+        for (int rb = 0; rb < NRB; rb++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) acc[rb][r] = 0.f;
+#pragma unroll
+        for (int s = 0; s < D; s++) {
+            const float bv = s < H ? x[s].re : x[s - H].im;
+#pragma unroll
+            for (int rb = 0; rb < NRB; rb++)
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rb][s], bv, acc[rb], 0, 0, 0);
+        }
+        if constexpr (D == 32) {
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const int i = 8 * (r >> 2) + 4 * kk + (r & 3);
+                st[base + offset(i)] = Cx<float>{acc[0][r], acc[1][r]};
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                st[base + offset(4 * kk + r)] = Cx<float>{acc[0][r], acc[0][r + 8]};
+                st[base + offset(8 + 4 * kk + r)] = Cx<float>{acc[0][r + 4], acc[0][r + 12]};
+            }
+        }
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(NT) k_init_zero(Cx<T> *__restrict__ state, uint64_t sstride,
                                                   uint64_t len) {
@@ -1512,10 +1608,33 @@ static void sweep_t(Cx<T> *state, uint64_t sstride, uint32_t nstates, int n, con
     }
 }
 
+bool dense_mfma_ok(int dtype, int n, const DevOp &op) {
+    static const int enabled = [] {
+        const char *v = std::getenv("QSIM_MFMA");
+        return v ? std::atoi(v) : 1;
+    }();
+    if (!enabled || dtype != QSIM_C64 || (op.k != 4 && op.k != 5) || n - op.k < 5) return false;
+    // the contraction does the dense work: worth it when at least half of the
+    // XOR diagonals are present
+    return __builtin_popcount(op.present) * 2 >= (1 << op.k);
+}
+
 int launch_sweep(int dtype, void *state, uint64_t sstride, uint32_t nstates, int n,
                  const DevOp &op, const void *coefs, hipStream_t st, uint64_t cstride,
                  const int32_t *status) {
     if (op.k < 1 || op.k > 5 || op.k > n) return QSIM_E_ARG;
+    if (dense_mfma_ok(dtype, n, op)) {
+        const uint64_t nblk = (uint64_t(1) << (n - op.k)) / 32;   // 32 groups per wave
+        const uint64_t blocks = std::min<uint64_t>((nblk + 3) / 4, 8192);
+        const dim3 grid(uint32_t(blocks), nstates);
+        if (op.k == 5)
+            hipLaunchKernelGGL(k_dense_mfma<5>, grid, dim3(NT), 0, st, (Cx<float> *)state, sstride, n, op,
+                               (const Cx<float> *)coefs, cstride, status);
+        else
+            hipLaunchKernelGGL(k_dense_mfma<4>, grid, dim3(NT), 0, st, (Cx<float> *)state, sstride, n, op,
+                               (const Cx<float> *)coefs, cstride, status);
+        return check(hipGetLastError());
+    }
     if (dtype == QSIM_C64)
         sweep_t<float>((Cx<float> *)state, sstride, nstates, n, op, (const Cx<float> *)coefs, cstride, status, st);
     else

@@ -119,6 +119,11 @@ int launch_tile(int dtype, void *state, uint64_t sstride, uint32_t nstates, cons
                 uint32_t ce, uint64_t cstride, const MeasArgs *ma, uint32_t flags,
                 hipStream_t st);
 
+// Whether launch_sweep applies `op` with the FP32 matrix cores (dense 4- or
+// 5-qubit operators on complex64 states of at least k + 5 qubits;
+// QSIM_MFMA=0 turns it off).
+bool dense_mfma_ok(int dtype, int n, const qs::DevOp &op);
+
 // One operator over the whole state (positions are global qubits); the
 // coefficients of state b start at coefs + b * cstride; states whose status
 // is nonzero are skipped.

@@ -231,11 +231,11 @@ class StateVector:
         check(_lib.qsim_init_zero(self.h), "qsim_init_zero")
 
     def qsim_apply(self, gates, mats=None, params=None, level=None, max_width=None,
-                   tile_qubits=None, flags=0):
+                   tile_qubits=None, flags=0, op_cost=None):
         g = np.ascontiguousarray(gates, dtype=GATE_DTYPE)
         m = None if mats is None else np.ascontiguousarray(mats, dtype=np.complex128)
         pr = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
-        o = _opts(level, max_width, tile_qubits, flags)
+        o = _opts(level, max_width, tile_qubits, flags, op_cost)
         check(_lib.qsim_apply(self.h, _p(g), len(g), _p(m), _n(m), _p(pr), _n(pr), C.byref(o) if o else None),
               "qsim_apply")
 

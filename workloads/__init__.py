@@ -433,6 +433,22 @@ def dense_brickwork_circuit(n: int, layers: int, seed: int = 41):
     return g, np.concatenate(mats) if mats else np.zeros(0, complex)
 
 
+def dense_operator_circuit(n: int, count: int, k: int = 5, seed: int = 43):
+    """`count` Haar-random k-qubit unitaries (MAT records) on random qubits:
+    every one a dense operator with all 2^k XOR shifts.  Returns
+    (gates, mats)."""
+    rng = _rng(seed, 6)
+    recs, mats = [], []
+    for _ in range(count):
+        qs = [int(q) for q in rng.choice(n, size=k, replace=False)]
+        recs.append((KIND_MAT, qs, ()))
+        mats.append(random_unitary(1 << k, rng).ravel())
+    g = gates(recs)
+    for i in range(len(g)):
+        g[i]["mat_off"] = i * (1 << (2 * k))
+    return g, np.concatenate(mats) if mats else np.zeros(0, complex)
+
+
 def random_state(n: int, seed: int) -> np.ndarray:
     """A normalised complex128 state with N(0,1) parts."""
     rng = _rng(seed, 98)
