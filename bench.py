@@ -58,6 +58,11 @@ def measured_traffic(dtype):
     return MEASURED_TRAFFIC.get(dtype) if kernel_source_hash() == MEASURED_TRAFFIC["kernels_sha256_16"] else None
 
 
+WORKLOAD_TEXT = {"pauli": "{} Pauli-string exponentials",
+                 "dense": "{} brick-wall layers of Haar-random two-qubit unitaries",
+                 "dense5": "{} Haar-random 5-qubit unitaries on random qubits"}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -632,7 +637,7 @@ def main():
         "vs_baseline": None,
         "dtype": "c128 (f64)" if args.dtype == "complex128" else "c64 (f32) + f64 reductions",
         "data": "synthetic",
-        "config": {"workload": f"{n}-qubit circuit of {args.n_exp} Pauli-string exponentials "
+        "config": {"workload": f"{n}-qubit circuit of {WORKLOAD_TEXT[args.workload].format(args.n_exp)} "
                                f"({st['input_gates']} gates), then <H> of a 100-term Pauli sum",
                    "qubits": n, "input_gates": st["input_gates"], "fused_ops": st["fused_ops"],
                    "ops_after_fusion_levels": st["ops_after"], "passes": st["passes"],
