@@ -65,7 +65,7 @@ def build(verbose: bool = False, out: str | None = None, extra_flags=(), csrc: s
                 print(out)
     tmp = lib_out + f".tmp{os.getpid()}"
     _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs,
-          f"-L{os.path.join(ROCM, 'lib')}", "-lamdhip64"])
+          f"-L{os.path.join(ROCM, 'lib')}", "-lamdhip64", "-lrocprofiler-sdk-roctx"])
     os.replace(tmp, lib_out)
     return lib_out
 
@@ -94,7 +94,8 @@ def build_sanitized(out_dir: str | None = None) -> str:
         list(ex.map(_run, jobs))
     lib = os.path.join(out_dir, "libqsim.so")
     _run([clang, "-shared", "-fPIC", "-pthread", "-fsanitize=address,undefined", "-shared-libsan", "-o", lib, *objs,
-          f"-L{os.path.join(ROCM, 'lib')}", "-lamdhip64", f"-Wl,-rpath,{os.path.join(ROCM, 'lib')}"])
+          f"-L{os.path.join(ROCM, 'lib')}", "-lamdhip64", "-lrocprofiler-sdk-roctx",
+          f"-Wl,-rpath,{os.path.join(ROCM, 'lib')}"])
     return lib
 
 

@@ -305,6 +305,7 @@ int compile_circuit(int n, int dtype, const qsim_gate *g, size_t ng, const GateI
 int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const GateInputs &in,
                     bool keep_params, bool allow_meas, int max_params,
                     const qsim_fuse_opts *opt, Compiled *out) {
+    TraceRange range("qsim.compile");
     double t0 = now_seconds();
     if (alloc_fault()) throw std::bad_alloc();
     FuseConfig fc;
@@ -312,10 +313,18 @@ int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const GateI
     default_configs(n, dtype, opt, &fc, &pc);
     fc.max_params = keep_params ? std::max(1, std::min(max_params, 3)) : 0;
     Lowered L;
-    int rc = lower(n, g, ng, in, keep_params, allow_meas, &L);
+    int rc;
+    {
+        TraceRange r("qsim.lower");
+        rc = lower(n, g, ng, in, keep_params, allow_meas, &L);
+    }
     if (rc) return rc;
     int64_t counts[6];
-    fuse(n, &L, fc, counts);
+    {
+        TraceRange r("qsim.fuse");
+        fuse(n, &L, fc, counts);
+    }
+    TraceRange plan_range("qsim.plan");
     std::vector<uint32_t> present(L.ops.size()), meta(L.ops.size());
     for (size_t i = 0; i < L.ops.size(); i++) {
         present[i] = op_present(L.ops[i], fc.sparse);
@@ -694,6 +703,7 @@ int qsim_init_zero(qsim_h h) {
 int qsim_apply(qsim_h h, const qsim_gate *g, size_t ng, const double *mats, size_t n_mats,
                const double *params, size_t n_params, const qsim_fuse_opts *opt) {
     if (!h || (ng && !g)) return QSIM_E_ARG;
+    TraceRange range("qsim_apply");
     Compiled c;
     int rc;
     try {
@@ -737,6 +747,7 @@ int qsim_compile(int n, int dtype, const qsim_gate *g, size_t ng, const double *
 
 int qsim_run(qsim_h h, qsim_prog p) {
     if (!h || !p || h->n != p->n || h->dtype != p->dtype) return QSIM_E_ARG;
+    TraceRange range("qsim_run");
     if (p->c.plan.ops.empty()) return QSIM_OK;
     if (p->graph_exec && p->graph_buf == h->buf) {
         return hip_rc(hipGraphLaunch(p->graph_exec, h->stream));
@@ -845,6 +856,7 @@ int qsim_measure(qsim_h h, int q, double u, int *outcome, double *p_outcome) {
     if (!h || !outcome || !p_outcome) return QSIM_E_ARG;
     if (q < 0 || q >= h->n) return QSIM_E_QUBIT;
     if (!(u >= 0.0 && u < 1.0)) return QSIM_E_ARG;
+    TraceRange range("qsim_measure");
     double P0, P1;
     int rc = weights01(h, q, &P0, &P1);
     if (rc) return rc;
@@ -862,6 +874,7 @@ int qsim_measure(qsim_h h, int q, double u, int *outcome, double *p_outcome) {
 int qsim_measure_assert(qsim_h h, int q, int want, double *p_want) {
     if (!h || !p_want || (want != 0 && want != 1)) return QSIM_E_ARG;
     if (q < 0 || q >= h->n) return QSIM_E_QUBIT;
+    TraceRange range("qsim_measure_assert");
     double P0, P1;
     int rc = weights01(h, q, &P0, &P1);
     if (rc) return rc;
@@ -932,6 +945,7 @@ int qsim_expval(qsim_h h, const qsim_pauli *t, size_t nt, double *out) {
     for (size_t k = 0; k < nt; k++) {
         if ((t[k].xmask & ~lim) || (t[k].zmask & ~lim) || !std::isfinite(t[k].coeff)) return QSIM_E_ARG;
     }
+    TraceRange range("qsim_expval");
     double nrm;
     int rc = qsim_norm(h, &nrm);
     if (rc) return rc;
@@ -977,6 +991,7 @@ int qsim_sample(qsim_h h, const double *u, size_t m, uint64_t *out) {
     if (!h || (m && (!u || !out))) return QSIM_E_ARG;
     for (size_t s = 0; s < m; s++)
         if (!(u[s] >= 0.0 && u[s] < 1.0)) return QSIM_E_ARG;
+    TraceRange range("qsim_sample");
     const uint64_t len = uint64_t(1) << h->n;
     const uint64_t nb = qk::scan_blocks(h->n);
     // layout: cum[len] | bsum[nb] | boff[nb] | u[m] | shots[m]

@@ -382,6 +382,7 @@ int qsim_batch_create(const qsim_batch_group *groups, int n_groups, const qsim_b
     if (!b) return QSIM_E_NOMEM;
     b->dtype = o.dtype;
     b->use_graph = o.use_graph != 0;
+    TraceRange range("qsim_batch_create");
     const double t0 = now_seconds();
     try {
         b->groups.resize(size_t(n_groups));
@@ -409,6 +410,7 @@ int qsim_batch_create(const qsim_batch_group *groups, int n_groups, const qsim_b
 
 int qsim_batch_run(qsim_batch_h b, void *hip_stream) {
     if (!b) return QSIM_E_ARG;
+    TraceRange range("qsim_batch_run");
     hipStream_t st = (hipStream_t)hip_stream;
     if (!b->use_graph) return enqueue_all(b, st);
     if (!b->graph_exec) {

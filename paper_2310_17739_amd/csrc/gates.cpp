@@ -12,6 +12,8 @@
 #include <chrono>
 #include <cmath>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "host.h"
 
 namespace qs {
@@ -20,6 +22,9 @@ double now_seconds() {
     using namespace std::chrono;
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
+
+TraceRange::TraceRange(const char *name) { roctxRangePushA(name); }
+TraceRange::~TraceRange() { roctxRangePop(); }
 
 namespace {
 

@@ -251,6 +251,17 @@ int pack_reg_pass(const std::vector<Op> &ops, const std::vector<uint32_t> &prese
 
 double now_seconds();
 
+// A named host range for profilers (roctx; `rocprofv3 --marker-trace` lists
+// them): pushed when constructed, popped when it leaves scope.  Ranges nest
+// per thread.  With no profiler attached a push and a pop cost a few tens of
+// nanoseconds, so they mark library calls and compile stages, not launches.
+struct TraceRange {
+    explicit TraceRange(const char *name);
+    ~TraceRange();
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
+
 // Allocation-failure injection for tests (qsim_debug_fail_alloc): true when
 // this allocation attempt is the one set to fail.  Every device and pinned
 // allocation of the library, and the start of every compile (standing for

@@ -206,6 +206,16 @@ def test_abi_exports_every_declared_symbol():
     assert not missing, missing
 
 
+def test_profiler_ranges_library_mapped():
+    """The library marks its calls and compile stages with roctx ranges
+    (shown by rocprofv3 --marker-trace); the roctx library is mapped once the
+    binding is loaded, and compiles run with the ranges in place."""
+    g = W.random_circuit(8, 60, seed=5)
+    assert qsim.qsim_debug_plan(8, g)["passes"] >= 1
+    maps = open("/proc/self/maps").read()
+    assert "librocprofiler-sdk-roctx" in maps
+
+
 def test_one_hip_runtime_after_import():
     """Importing the binding in a fresh process (before anything else loads
     torch) maps a single HIP runtime: the library shares torch's."""
