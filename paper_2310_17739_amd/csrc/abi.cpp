@@ -952,7 +952,7 @@ int qsim_expval(qsim_h h, const qsim_pauli *t, size_t nt, double *out) {
     if (!(nrm > 0)) return QSIM_E_ZERO_PROB;
     if (nt == 0) { *out = 0.0; return QSIM_OK; }
     std::vector<uint64_t> table;
-    const uint32_t nrows = qk::pauli_rows(t, nt, &table);
+    const qk::PauliRows nrows = qk::pauli_rows(t, nt, &table);
     rc = grow(&h->d_masks, &h->cap_masks, 8 * table.size(), h->stream);
     if (rc) return rc;
     uint64_t *dm = (uint64_t *)h->d_masks;

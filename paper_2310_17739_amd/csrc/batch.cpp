@@ -67,7 +67,8 @@ struct Group {
     double *d_norm = nullptr;      // [nstates]
     uint64_t *d_masks = nullptr;   // [2][nterms]
     double *d_pauli = nullptr;     // [nstates][nterms][2]
-    uint32_t pauli_chunks = 0, norm_chunks = 0, pauli_rows = 0;
+    uint32_t pauli_chunks = 0, norm_chunks = 0;
+    qk::PauliRows pauli_rows;
     int64_t coef_bytes = 0;
     int tuned_width = 0;           // fusion width the autotuner chose (0: not tuned)
     double tune_seconds = 0.0;

@@ -482,32 +482,41 @@ int union_lists(const int *a, int ka, const int *b, int kb, int *uq) {
 // run's partial products may be dense -- half of a CNOT ladder -- while the
 // whole run is sparse -- the Pauli-string exponential the ladder implements
 // -- which a merge judged one step at a time does not reach.
+// The runs that start at one operator: for e = s + 1 .. s + n, the terms and
+// width of the product of operators s .. e - 1.
+constexpr int kMaxRun = 64;
+struct RunTable {
+    uint8_t n = 0;
+    uint8_t terms[kMaxRun];
+    uint8_t k[kMaxRun];
+};
+
 void fuse_runs(Lowered *L, const FuseConfig &cfg) {
     const double tol = 1e-14;
     const size_t N = L->ops.size();
-    const int kMaxRun = 64;
     std::vector<double> best(N + 1, 1e300);
     std::vector<int> from(N + 1, -1);
     best[0] = 0;
     bool any_params = false;
     for (const Op &o : L->ops) any_params = any_params || o.np > 0;
-    auto relax = [&](size_t s, size_t e, int terms, int k) {
-        const double c = best[s] + (cfg.sparse ? terms : (1 << k)) + cfg.lds_cost;
-        if (c < best[e]) {
-            best[e] = c;
-            from[e] = int(s);
-        }
-    };
+    std::vector<uint32_t> gp;
     if (!any_params) {
-        // products of runs in XOR-shift form (no angle slots to carry)
-        std::vector<uint32_t> gp(N);
+        gp.resize(N);
         for (size_t i = 0; i < N; i++) gp[i] = exact_present(L->ops[i]);
-        std::unique_ptr<XOp> buf0(new XOp), buf1(new XOp);
-        for (size_t s = 0; s < N; s++) {
-            if (best[s] >= 1e299) continue;
-            XOp *cur = buf0.get(), *nxt = buf1.get();
+    }
+    // the products of the runs from s (independent of the cost so far)
+    auto table = [&](size_t s, XOp *b0, XOp *b1, RunTable *t) {
+        t->n = 0;
+        auto put = [&](int terms, int k) {
+            t->terms[t->n] = uint8_t(terms);
+            t->k[t->n] = uint8_t(k);
+            t->n++;
+        };
+        if (!any_params) {
+            // products in XOR-shift form (no angle slots to carry)
+            XOp *cur = b0, *nxt = b1;
             xop_from(L->ops[s], gp[s], cur);
-            relax(s, s + 1, xop_terms(*cur, tol), cur->k);
+            put(xop_terms(*cur, tol), cur->k);
             for (size_t e = s + 2; e <= N && int(e - s) <= kMaxRun; e++) {
                 const Op &o = L->ops[e - 1];
                 if (L->op_epoch[e - 1] != L->op_epoch[s]) break;
@@ -520,12 +529,9 @@ void fuse_runs(Lowered *L, const FuseConfig &cfg) {
                 }
                 xop_left_mul(o, gp[e - 1], *cur, nxt);
                 std::swap(cur, nxt);
-                relax(s, e, xop_terms(*cur, tol), cur->k);
+                put(xop_terms(*cur, tol), cur->k);
             }
-        }
-    } else {
-        for (size_t s = 0; s < N; s++) {
-            if (best[s] >= 1e299) continue;
+        } else {
             Op cur = L->ops[s];
             for (size_t e = s + 1; e <= N && int(e - s) <= kMaxRun; e++) {
                 if (e > s + 1) {
@@ -538,7 +544,42 @@ void fuse_runs(Lowered *L, const FuseConfig &cfg) {
                     cur = expand(cur, uq, uk);
                     mul_small(&cur, o, true);
                 }
-                relax(s, e, cfg.sparse ? op_terms(cur, tol) : 0, cur.k);
+                put(cfg.sparse ? op_terms(cur, tol) : 0, cur.k);
+            }
+        }
+    };
+    // blocks of starts: their tables on several threads, then the dynamic
+    // programme over the block in order
+    const size_t kBlock = 8192;
+    const int nth = std::max(1, std::min(16, int(std::thread::hardware_concurrency())));
+    std::vector<RunTable> tab(std::min(kBlock, N));
+    for (size_t b0 = 0; b0 < N; b0 += kBlock) {
+        const size_t nb = std::min(kBlock, N - b0);
+        const int use = int(std::min<size_t>(size_t(nth), (nb + 255) / 256));
+        std::vector<char> failed(size_t(use), 0);
+        auto work = [&](int w) {
+            try {
+                std::unique_ptr<XOp> x0(new XOp), x1(new XOp);
+                for (size_t i = size_t(w); i < nb; i += size_t(use)) table(b0 + i, x0.get(), x1.get(), &tab[i]);
+            } catch (const std::bad_alloc &) {
+                failed[size_t(w)] = 1;
+            }
+        };
+        std::vector<std::thread> th;
+        for (int w = 1; w < use; w++) th.emplace_back(work, w);
+        work(0);
+        for (auto &x : th) x.join();
+        for (char f : failed)
+            if (f) throw std::bad_alloc();
+        for (size_t i = 0; i < nb; i++) {
+            const size_t s = b0 + i;
+            for (int j = 0; j < tab[i].n; j++) {
+                const size_t e = s + 1 + size_t(j);
+                const double c = best[s] + (cfg.sparse ? tab[i].terms[j] : (1 << tab[i].k[j])) + cfg.lds_cost;
+                if (c < best[e]) {
+                    best[e] = c;
+                    from[e] = int(s);
+                }
             }
         }
     }

@@ -1196,7 +1196,7 @@ __global__ void __launch_bounds__(NT) k_marginal(const Cx<T> *__restrict__ state
 // (-1)^popcount(x & z_k), to every term k of the row.  Each term's sums run
 // in the same order as they would alone.
 // partials[((b * nterms + k) * 2 + comp) * nchunks + chunk]
-template <typename T>
+template <typename T, int R>
 __global__ void __launch_bounds__(NT) k_pauli(const Cx<T> *__restrict__ state, uint64_t sstride,
                                               int n, const uint64_t *__restrict__ zmask,
                                               const uint64_t *__restrict__ rows, uint32_t nterms,
@@ -1206,20 +1206,20 @@ __global__ void __launch_bounds__(NT) k_pauli(const Cx<T> *__restrict__ state, u
     const uint64_t *row = rows + size_t(blockIdx.y) * (2 + kPauliRow);
     const uint64_t xm = row[0];
     const int cnt = int(row[1]);
-    uint64_t z[kPauliRow];
+    uint64_t z[R];
 #pragma unroll
-    for (int j = 0; j < kPauliRow; j++) z[j] = j < cnt ? zmask[row[2 + j]] : 0;
+    for (int j = 0; j < R; j++) z[j] = j < cnt ? zmask[row[2 + j]] : 0;
     const uint64_t per = (uint64_t(1) << n) / nchunks;
-    double acc[2 * kPauliRow];
+    double acc[2 * R];
 #pragma unroll
-    for (int j = 0; j < 2 * kPauliRow; j++) acc[j] = 0.0;
+    for (int j = 0; j < 2 * R; j++) acc[j] = 0.0;
     for (uint64_t x = uint64_t(chunk) * per + threadIdx.x; x < uint64_t(chunk + 1) * per; x += NT) {
         const Cx<T> a = st[x], c = st[x ^ xm];
         const double ar = double(a.re), ai = double(a.im), cr = double(c.re), ci = double(c.im);
         // conj(c) * a
         const double re = cr * ar + ci * ai, im = cr * ai - ci * ar;
 #pragma unroll
-        for (int j = 0; j < kPauliRow; j++) {
+        for (int j = 0; j < R; j++) {
             if (j < cnt) {
                 const bool odd = __builtin_popcountll(x & z[j]) & 1;
                 acc[2 * j] += odd ? -re : re;
@@ -1227,7 +1227,7 @@ __global__ void __launch_bounds__(NT) k_pauli(const Cx<T> *__restrict__ state, u
             }
         }
     }
-    block_sum<2 * kPauliRow>(acc);
+    block_sum<2 * R>(acc);
     if (threadIdx.x == 0) {
         for (int j = 0; j < cnt; j++) {
             const size_t o = (size_t(blockIdx.z) * nterms + size_t(row[2 + j])) * 2;
@@ -1759,40 +1759,70 @@ uint32_t pauli_chunks(int n) {
     return uint32_t(c);
 }
 
-uint32_t pauli_rows(const qsim_pauli *t, size_t nt, std::vector<uint64_t> *table) {
+namespace {
+int pauli_bucket(size_t cnt) { return cnt > 4 ? 0 : cnt > 2 ? 1 : cnt == 2 ? 2 : 3; }
+}  // namespace
+
+PauliRows pauli_rows(const qsim_pauli *t, size_t nt, std::vector<uint64_t> *table) {
     std::vector<uint32_t> idx(nt);
     for (size_t k = 0; k < nt; k++) idx[k] = uint32_t(k);
     std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) { return t[a].xmask < t[b].xmask; });
-    table->assign(nt, 0);
-    for (size_t k = 0; k < nt; k++) (*table)[k] = t[k].zmask;
-    uint32_t rows = 0;
+    // rows as (first sorted index, count), then ordered by bucket
+    std::vector<std::pair<size_t, size_t>> rows;
     for (size_t i = 0; i < nt;) {
         size_t j = i;
         while (j < nt && j - i < size_t(kPauliRow) && t[idx[j]].xmask == t[idx[i]].xmask) j++;
-        table->push_back(t[idx[i]].xmask);
-        table->push_back(uint64_t(j - i));
-        for (int s = 0; s < kPauliRow; s++) table->push_back(i + s < j ? idx[i + s] : 0);
-        rows++;
+        rows.push_back({i, j - i});
         i = j;
     }
-    return rows;
+    std::stable_sort(rows.begin(), rows.end(), [](const std::pair<size_t, size_t> &a,
+                                                  const std::pair<size_t, size_t> &b) {
+        return pauli_bucket(a.second) < pauli_bucket(b.second);
+    });
+    table->assign(nt, 0);
+    for (size_t k = 0; k < nt; k++) (*table)[k] = t[k].zmask;
+    PauliRows pr;
+    for (const auto &r : rows) {
+        table->push_back(t[idx[r.first]].xmask);
+        table->push_back(uint64_t(r.second));
+        for (int s = 0; s < kPauliRow; s++) table->push_back(size_t(s) < r.second ? idx[r.first + s] : 0);
+        pr.bucket[pauli_bucket(r.second)]++;
+        pr.rows++;
+    }
+    return pr;
 }
 
 int launch_pauli(int dtype, const void *state, uint64_t sstride, uint32_t nstates, int n,
-                 const uint64_t *table, int nterms, uint32_t nrows, double *partials,
+                 const uint64_t *table, int nterms, const PauliRows &pr, double *partials,
                  double *out, hipStream_t st, uint32_t nchunks_override) {
     if (nterms <= 0) return QSIM_OK;
-    if (nrows == 0 || nrows > uint32_t(nterms)) return QSIM_E_ARG;
+    const uint32_t nrows = pr.bucket[0] + pr.bucket[1] + pr.bucket[2] + pr.bucket[3];
+    if (pr.rows == 0 || nrows != pr.rows || pr.rows > uint32_t(nterms)) return QSIM_E_ARG;
     uint32_t nchunks = pauli_chunks(n);
     if (nchunks_override && nchunks_override < nchunks) nchunks = nchunks_override;
-    const dim3 grid(nchunks, nrows, nstates);
     const uint64_t *rows = table + nterms;
-    if (dtype == QSIM_C64)
-        hipLaunchKernelGGL(k_pauli<float>, grid, dim3(NT), 0, st, (const Cx<float> *)state, sstride, n, table, rows,
-                           uint32_t(nterms), partials);
-    else
-        hipLaunchKernelGGL(k_pauli<double>, grid, dim3(NT), 0, st, (const Cx<double> *)state, sstride, n, table, rows,
-                           uint32_t(nterms), partials);
+    const int64_t stride = 2 + kPauliRow;
+    for (int b = 0; b < 4; b++) {
+        if (pr.bucket[b] == 0) {
+            continue;
+        }
+        const dim3 grid(nchunks, pr.bucket[b], nstates);
+#define QK_PAULI(R)                                                                                         \
+    if (dtype == QSIM_C64)                                                                                  \
+        hipLaunchKernelGGL((k_pauli<float, R>), grid, dim3(NT), 0, st, (const Cx<float> *)state, sstride, n, \
+                           table, rows, uint32_t(nterms), partials);                                        \
+    else                                                                                                    \
+        hipLaunchKernelGGL((k_pauli<double, R>), grid, dim3(NT), 0, st, (const Cx<double> *)state, sstride,  \
+                           n, table, rows, uint32_t(nterms), partials);
+        switch (b) {
+        case 0: QK_PAULI(8) break;
+        case 1: QK_PAULI(4) break;
+        case 2: QK_PAULI(2) break;
+        default: QK_PAULI(1) break;
+        }
+#undef QK_PAULI
+        rows += stride * int64_t(pr.bucket[b]);
+    }
     hipLaunchKernelGGL(k_finish, dim3(uint32_t(nstates) * uint32_t(nterms) * 2), dim3(NT), 0, st,
                        partials, nchunks, out);
     return check(hipGetLastError());

@@ -192,11 +192,17 @@ int launch_probs_noalloc(int dtype, const void *state, int n, const int *qs, int
 // (complex, FP64), written as out[(b * nterms + k) * 2 + {0,1}].  Terms that
 // share an X mask share one read of the state: pauli_rows builds the device
 // table (the zmask of every term, then rows of up to kPauliRow terms with a
-// common X mask: xmask, count, term indices) and returns the row count.
+// common X mask: xmask, count, term indices).  Rows are ordered by the
+// kernel width that serves them (5-8 terms, 3-4, 2, 1), so that a row pays
+// only for the accumulators it uses; `bucket` holds the row count of each.
 constexpr int kPauliRow = 8;
-uint32_t pauli_rows(const qsim_pauli *t, size_t nt, std::vector<uint64_t> *table);
+struct PauliRows {
+    uint32_t rows = 0;
+    uint32_t bucket[4] = {0, 0, 0, 0};   // rows served by widths 8, 4, 2, 1
+};
+PauliRows pauli_rows(const qsim_pauli *t, size_t nt, std::vector<uint64_t> *table);
 int launch_pauli(int dtype, const void *state, uint64_t sstride, uint32_t nstates, int n,
-                 const uint64_t *table, int nterms, uint32_t nrows, double *partials,
+                 const uint64_t *table, int nterms, const PauliRows &rows, double *partials,
                  double *out, hipStream_t st, uint32_t nchunks = 0);
 uint32_t pauli_chunks(int n);
 

@@ -228,7 +228,7 @@ int launch_request(qsim_server *s, Slot &sl, Request *r) {
     if ((rc = qk::launch_marginal(dtype, state, 0, 1, r->n, nullptr, 0, d_part, d_out, sl.st))) return rc;
     if (nt) {
         std::vector<uint64_t> m;
-        const uint32_t nrows = qk::pauli_rows(r->terms.data(), nt, &m);
+        const qk::PauliRows nrows = qk::pauli_rows(r->terms.data(), nt, &m);
         if ((rc = grow_dev((void **)&sl.d_masks, &sl.cap_masks, 8 * m.size()))) return rc;
         // synchronous copy: the slot's previous request has completed
         if ((rc = qk::note_hip(hipMemcpy(sl.d_masks, m.data(), 8 * m.size(), hipMemcpyHostToDevice), "masks")))

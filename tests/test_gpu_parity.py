@@ -194,8 +194,10 @@ def test_probs_norm_expval(Q, dtype):
 @pytest.mark.parametrize("dtype", ["complex128", "complex64"])
 def test_expval_terms_sharing_x_masks(Q, dtype):
     """Terms with a common X mask share one read of the state (rows of up to
-    8 terms): all-Z terms, 11 terms on one X mask (two rows), and singles,
-    in scrambled order; each term and the sum against the oracle."""
+    8 terms, served by kernels for rows of 8, 4, 2 and 1 terms): all-Z
+    terms, 11 terms on one X mask (two rows), X masks with 2, 4 and 6
+    terms, and singles, in scrambled order; each term and the sum against
+    the oracle."""
     n = 16
     g, _, _ = W.pauli_exponential_circuit(n, 150, seed=31)
     sv = run_gpu(Q, n, g, dtype)
@@ -207,6 +209,9 @@ def test_expval_terms_sharing_x_masks(Q, dtype):
     xm = (1 << 3) | (1 << 9) | (1 << 14)
     for j in range(11):
         terms.append((rng.normal(), xm, int(rng.integers(0, 1 << n))))
+    for cnt, xo in ((2, (1 << 0) | (1 << 5)), (4, 1 << 12), (6, (1 << 2) | (1 << 7) | (1 << 15))):
+        for j in range(cnt):
+            terms.append((rng.normal(), xo, int(rng.integers(0, 1 << n))))
     H0 = W.pauli_sum(n, 12, seed=5)
     for t in H0:
         terms.append((float(t["coeff"]), int(t["xmask"]), int(t["zmask"])))
