@@ -587,19 +587,38 @@ void fuse_runs(Lowered *L, const FuseConfig &cfg) {
     std::vector<std::pair<int, int>> runs;
     for (int e = int(N); e > 0; e = from[e]) runs.push_back({from[e], e});
     std::reverse(runs.begin(), runs.end());
-    std::vector<Op> out;
-    std::vector<int> out_ep;
-    out.reserve(runs.size());
-    for (const auto &r : runs) {
-        Op cur = L->ops[size_t(r.first)];
-        for (int i = r.first + 1; i < r.second; i++) {
-            int uq[2 * kMaxK];
-            const int uk = union_qubits(cur, L->ops[size_t(i)], uq);
-            cur = expand(cur, uq, uk);
-            mul_small(&cur, L->ops[size_t(i)], true);
+    // each run's dense product (independent of the others: several threads,
+    // each on a contiguous range of runs)
+    std::vector<Op> out(runs.size());
+    std::vector<int> out_ep(runs.size());
+    const size_t nr = runs.size();
+    const int use = int(std::min<size_t>(size_t(nth), (nr + 1023) / 1024));
+    std::vector<char> failed(size_t(std::max(use, 1)), 0);
+    auto rebuild = [&](int w) {
+        try {
+            for (size_t j = nr * size_t(w) / size_t(use); j < nr * size_t(w + 1) / size_t(use); j++) {
+                const auto &r = runs[j];
+                Op cur = L->ops[size_t(r.first)];
+                for (int i = r.first + 1; i < r.second; i++) {
+                    int uq[2 * kMaxK];
+                    const int uk = union_qubits(cur, L->ops[size_t(i)], uq);
+                    cur = expand(cur, uq, uk);
+                    mul_small(&cur, L->ops[size_t(i)], true);
+                }
+                out_ep[j] = L->op_epoch[size_t(r.first)];
+                out[j] = std::move(cur);
+            }
+        } catch (const std::bad_alloc &) {
+            failed[size_t(w)] = 1;
         }
-        out_ep.push_back(L->op_epoch[size_t(r.first)]);
-        out.push_back(std::move(cur));
+    };
+    if (use > 0) {
+        std::vector<std::thread> th;
+        for (int w = 1; w < use; w++) th.emplace_back(rebuild, w);
+        rebuild(0);
+        for (auto &x : th) x.join();
+        for (char f : failed)
+            if (f) throw std::bad_alloc();
     }
     L->ops.swap(out);
     L->op_epoch.swap(out_ep);
