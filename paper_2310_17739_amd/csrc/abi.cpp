@@ -58,17 +58,24 @@ int resident_max(int dtype) {
     return dtype == QSIM_C64 ? 14 : 13;
 }
 
+// 12-qubit tiles while a pass gives each CU at most a few of them; complex64
+// passes with many tiles (2,048 or more 12-qubit tiles over all the states
+// the pass covers: one state of 23+ qubits, or a batch of smaller ones) take
+// 13-qubit tiles: several tiles are then queued per CU, so loads, operators
+// and stores of different tiles overlap, and the larger tiles carry more
+// operators per pass
+int default_tile_qubits(int n, int dtype, uint64_t nstates) {
+    const bool many = dtype == QSIM_C64 && n > 12 && (nstates << (n - 12)) >= 2048;
+    return env_int("QSIM_TILE_QUBITS", many ? 13 : 12);
+}
+
 void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc, PlanConfig *pc) {
     fc->level = 5;
     fc->max_width = 4;
     fc->sparse = true;
     fc->max_params = 0;
     pc->one_op_per_pass = false;
-    // 12-qubit tiles while a state gives each CU at most a few of them; for
-    // complex64 states of 23+ qubits (several tiles queued per CU, so loads,
-    // operators and stores of different tiles overlap) 13-qubit tiles, whose
-    // passes carry more operators
-    pc->tile_qubits = env_int("QSIM_TILE_QUBITS", (dtype == QSIM_C64 && n >= 23) ? 13 : 12);
+    pc->tile_qubits = default_tile_qubits(n, dtype, 1);
     pc->low_qubits = env_int("QSIM_LOW_QUBITS", dtype == QSIM_C64 ? 4 : 3);
     pc->window = env_int("QSIM_PLAN_WINDOW", 1024);
     pc->max_tile_k = 4;

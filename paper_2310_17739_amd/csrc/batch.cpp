@@ -158,7 +158,13 @@ int setup_group(Group &G, const qsim_batch_group &in, int dtype, const qsim_batc
     G.sstride = uint64_t(1) << in.n;
     const size_t elem = elem_bytes(dtype);
     const bool param = in.params != nullptr && in.n_params > 0;
-    const qsim_fuse_opts *fo = (opt.fuse.level > 0) ? &opt.fuse : nullptr;
+    // the group's passes cover all its states: its default tile width
+    // follows their total tile count
+    qsim_fuse_opts base{};
+    if (opt.fuse.level > 0) base = opt.fuse;
+    else base.level = 5;
+    if (base.tile_qubits <= 0) base.tile_qubits = default_tile_qubits(in.n, dtype, uint64_t(in.n_states));
+    const qsim_fuse_opts *fo = &base;
     qsim_fuse_opts tuned{};
     if (opt.autotune) {
         // the template's fusion width, timed on its first instance (angles of

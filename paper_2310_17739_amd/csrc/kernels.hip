@@ -1191,10 +1191,14 @@ __global__ void __launch_bounds__(NT) k_marginal(const Cx<T> *__restrict__ state
 }
 
 // Pauli overlaps of up to kPauliRow terms that share an X mask (one row of
-// the table built by pauli_rows): each amplitude pair (a[x], a[x ^ X]) is
-// read once and its product conj(a[x ^ X]) a[x] added, with the sign
-// (-1)^popcount(x & z_k), to every term k of the row.  Each term's sums run
-// in the same order as they would alone.
+// the table built by pauli_rows), S_k = sum_x s_k(x) conj(a[x ^ X]) a[x] with
+// s_k(x) = (-1)^popcount(x & z_k).  For X != 0 the sum runs over the pairs
+// {x, x ^ X} with bit h of x clear (h the highest bit of X), each amplitude
+// read once: with p = conj(a[x ^ X]) a[x], the pair adds
+// s_k(x) (p + sigma_k conj(p)), sigma_k = (-1)^popcount(X & z_k), which is
+// 2 s_k(x) Re p when sigma_k = 1 and 2i s_k(x) Im p otherwise.  For X = 0,
+// S_k = sum_x s_k(x) |a[x]|^2.  Each term's sums run in the same order as
+// they would alone.
 // partials[((b * nterms + k) * 2 + comp) * nchunks + chunk]
 template <typename T, int R>
 __global__ void __launch_bounds__(NT) k_pauli(const Cx<T> *__restrict__ state, uint64_t sstride,
@@ -1209,21 +1213,41 @@ __global__ void __launch_bounds__(NT) k_pauli(const Cx<T> *__restrict__ state, u
     uint64_t z[R];
 #pragma unroll
     for (int j = 0; j < R; j++) z[j] = j < cnt ? zmask[row[2 + j]] : 0;
-    const uint64_t per = (uint64_t(1) << n) / nchunks;
     double acc[2 * R];
 #pragma unroll
     for (int j = 0; j < 2 * R; j++) acc[j] = 0.0;
-    for (uint64_t x = uint64_t(chunk) * per + threadIdx.x; x < uint64_t(chunk + 1) * per; x += NT) {
-        const Cx<T> a = st[x], c = st[x ^ xm];
-        const double ar = double(a.re), ai = double(a.im), cr = double(c.re), ci = double(c.im);
-        // conj(c) * a
-        const double re = cr * ar + ci * ai, im = cr * ai - ci * ar;
+    if (xm == 0) {
+        const uint64_t per = (uint64_t(1) << n) / nchunks;
+        for (uint64_t x = uint64_t(chunk) * per + threadIdx.x; x < uint64_t(chunk + 1) * per; x += NT) {
+            const double w = norm2(st[x]);
 #pragma unroll
-        for (int j = 0; j < R; j++) {
-            if (j < cnt) {
-                const bool odd = __builtin_popcountll(x & z[j]) & 1;
-                acc[2 * j] += odd ? -re : re;
-                acc[2 * j + 1] += odd ? -im : im;
+            for (int j = 0; j < R; j++) {
+                if (j < cnt) {
+                    const bool odd = __builtin_popcountll(x & z[j]) & 1;
+                    acc[2 * j] += odd ? -w : w;
+                }
+            }
+        }
+    } else {
+        const int h = 63 - __builtin_clzll(xm);
+        const uint64_t lowm = (uint64_t(1) << h) - 1;
+        bool real_part[R];
+#pragma unroll
+        for (int j = 0; j < R; j++) real_part[j] = !(__builtin_popcountll(xm & z[j]) & 1);
+        const uint64_t per = (uint64_t(1) << (n - 1)) / nchunks;
+        for (uint64_t y = uint64_t(chunk) * per + threadIdx.x; y < uint64_t(chunk + 1) * per; y += NT) {
+            const uint64_t x = ((y >> h) << (h + 1)) | (y & lowm);
+            const Cx<T> a = st[x], c = st[x ^ xm];
+            const double ar = double(a.re), ai = double(a.im), cr = double(c.re), ci = double(c.im);
+            // 2 conj(c) * a
+            const double re = 2.0 * (cr * ar + ci * ai), im = 2.0 * (cr * ai - ci * ar);
+#pragma unroll
+            for (int j = 0; j < R; j++) {
+                if (j < cnt) {
+                    const bool odd = __builtin_popcountll(x & z[j]) & 1;
+                    if (real_part[j]) acc[2 * j] += odd ? -re : re;
+                    else acc[2 * j + 1] += odd ? -im : im;
+                }
             }
         }
     }

@@ -42,6 +42,9 @@ struct DeviceTables {
 size_t elem_bytes(int dtype);
 int env_int(const char *name, int dflt);
 int resident_max(int dtype);
+// Default tile width for passes over `nstates` states of n qubits
+// (QSIM_TILE_QUBITS overrides it).
+int default_tile_qubits(int n, int dtype, uint64_t nstates);
 void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc, PlanConfig *pc);
 int compile_circuit(int n, int dtype, const qsim_gate *g, size_t ng, const GateInputs &in,
                     const qsim_fuse_opts *opt, Compiled *out);
