@@ -223,7 +223,9 @@ def run_batched(qsim, W, n_circuits=4096, n_exp=500, sample_one_at_a_time=48):
     t0 = time.perf_counter()
     b = qsim.Batch(groups, dtype="complex64", use_graph=True, autotune=True)
     create_s = time.perf_counter() - t0
-    widths_tuned = {int(gd["n"]): b.qsim_batch_group_stats(gi)["tuned_width"] for gi, gd in enumerate(groups)}
+    gstats = [b.qsim_batch_group_stats(gi) for gi in range(len(groups))]
+    widths_tuned = {int(gd["n"]): gs["tuned_width"] for gd, gs in zip(groups, gstats)}
+    tiles_tuned = {int(gd["n"]): gs["tile_qubits"] for gd, gs in zip(groups, gstats)}
     t0 = time.perf_counter()
     b.qsim_batch_run()
     torch.cuda.synchronize()
@@ -274,7 +276,8 @@ def run_batched(qsim, W, n_circuits=4096, n_exp=500, sample_one_at_a_time=48):
             "first_run_s": first_s,
             "circuits_per_s_with_create": n_circuits / (create_s + first_s),
             "state_bytes": info["state_bytes"], "passes": info["passes"],
-            "tuned_fusion_width_by_qubits": widths_tuned, "tune_s": info["tune_seconds"],
+            "tuned_fusion_width_by_qubits": widths_tuned, "tile_qubits_by_qubits": tiles_tuned,
+            "tune_s": info["tune_seconds"],
             "one_at_a_time_c128_circuits_per_s": 1.0 / one_run,
             "one_at_a_time_c128_circuits_per_s_with_compile": 1.0 / one_all,
             "one_at_a_time_sample": int(len(pick)),

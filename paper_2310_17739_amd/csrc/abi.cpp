@@ -516,7 +516,7 @@ void free_tables(DeviceTables *dt) {
 }
 
 int enqueue_passes(const Compiled &c, const DeviceTables &dt, int dtype, void *state,
-                   hipStream_t st, bool init_zero_first) {
+                   hipStream_t st, bool init_zero_first, uint64_t sstride, uint32_t nstates) {
     const PackedPlan &p = c.plan;
     for (size_t i = 0; i < c.passes.size(); i++) {
         const PassInfo &pi = c.passes[i];
@@ -525,17 +525,17 @@ int enqueue_passes(const Compiled &c, const DeviceTables &dt, int dtype, void *s
         if (pi.kind == Pass::MEASURE) return QSIM_E_UNSUPPORTED;
         if (pi.strided) {
             for (uint32_t j = ob; j < oe; j++) {
-                rc = qk::launch_sweep(dtype, state, 0, 1, pi.ta.n, p.ops[j], dt.d_coefs, st);
+                rc = qk::launch_sweep(dtype, state, sstride, nstates, pi.ta.n, p.ops[j], dt.d_coefs, st);
                 if (rc) return rc;
             }
         } else if (pi.reg) {
             uint32_t flags = (init_zero_first && i == 0) ? qk::TF_INIT_ZERO : 0u;
-            rc = qk::launch_reg(dtype, state, 0, 1, pi.ra, dt.d_ops, ob, oe, dt.d_coefs, p.coef_begin[i],
-                                p.coef_begin[i + 1], 0, nullptr, flags, st);
+            rc = qk::launch_reg(dtype, state, sstride, nstates, pi.ra, dt.d_ops, ob, oe, dt.d_coefs,
+                                p.coef_begin[i], p.coef_begin[i + 1], 0, nullptr, flags, st);
             if (rc) return rc;
         } else {
             uint32_t flags = (init_zero_first && i == 0) ? qk::TF_INIT_ZERO : 0u;
-            rc = qk::launch_tile(dtype, state, 0, 1, pi.ta, dt.d_ops, ob, oe, dt.d_coefs,
+            rc = qk::launch_tile(dtype, state, sstride, nstates, pi.ta, dt.d_ops, ob, oe, dt.d_coefs,
                                  p.coef_begin[i], p.coef_begin[i + 1], 0, nullptr, flags, st);
             if (rc) return rc;
         }
@@ -1155,6 +1155,66 @@ int tune_width(int n, int dtype, const qsim_gate *g, size_t ng, const GateInputs
         if (!rc && ns < *best_ns) {
             *best_ns = ns;
             *best_w = w;
+        }
+    }
+    if (st) (void)hipStreamSynchronize(st);
+    free_tables(&dt);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    (void)hipFree(buf);
+    return rc;
+}
+
+int tune_tile_batch(int n, int dtype, const qsim_gate *g, size_t ng, const GateInputs &in,
+                    const qsim_fuse_opts &base, uint32_t nstates, int *best_t) {
+    *best_t = base.tile_qubits;
+    if (n <= resident_max(dtype) || nstates == 0) return QSIM_OK;
+    // enough states for 4,096 12-qubit tiles (16 per CU), within 1 GiB
+    const size_t state_bytes = elem_bytes(dtype) << n;
+    uint64_t sample = std::max<uint64_t>(1, uint64_t(4096) >> std::min(n - 12, 12));
+    sample = std::min<uint64_t>(sample, nstates);
+    sample = std::max<uint64_t>(1, std::min<uint64_t>(sample, (uint64_t(1) << 30) / state_bytes));
+    void *buf = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (alloc_fault() || hipMalloc(&buf, state_bytes * sample) != hipSuccess) {
+        (void)hipGetLastError();
+        return QSIM_E_NOMEM;
+    }
+    int rc = hip_rc(hipStreamCreate(&st));
+    if (!rc) rc = hip_rc(hipEventCreate(&e0));
+    if (!rc) rc = hip_rc(hipEventCreate(&e1));
+    DeviceTables dt;
+    double best_ms = 1e300;
+    for (int t = 12; t <= 13 && !rc; t++) {
+        qsim_fuse_opts o = base;
+        o.tile_qubits = t;
+        Compiled c;
+        try {
+            rc = compile_circuit(n, dtype, g, ng, in, &o, &c);
+        } catch (const std::bad_alloc &) {
+            rc = QSIM_E_NOMEM;
+        }
+        if (rc) break;
+        if (c.plan.ops.empty()) break;
+        if ((rc = upload_plan(&dt, dtype, c.plan, st))) break;
+        const uint64_t sstride = uint64_t(1) << n;
+        // warm, then the best of three timed runs
+        if ((rc = enqueue_passes(c, dt, dtype, buf, st, true, sstride, uint32_t(sample)))) break;
+        double run_ms = 1e300;
+        for (int rep = 0; rep < 3 && !rc; rep++) {
+            (void)hipEventRecord(e0, st);
+            if ((rc = enqueue_passes(c, dt, dtype, buf, st, true, sstride, uint32_t(sample)))) break;
+            (void)hipEventRecord(e1, st);
+            if ((rc = hip_rc(hipEventSynchronize(e1)))) break;
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            run_ms = std::min(run_ms, double(ms));
+        }
+        if (!rc && run_ms < best_ms) {
+            best_ms = run_ms;
+            *best_t = t;
         }
     }
     if (st) (void)hipStreamSynchronize(st);

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -168,9 +169,10 @@ int setup_group(Group &G, const qsim_batch_group &in, int dtype, const qsim_batc
     qsim_fuse_opts tuned{};
     if (opt.autotune) {
         // the template's fusion width, timed on its first instance (angles of
-        // state 0 bound on the host); measurement records are left out of the
-        // timed circuit, and the tile and low-qubit choices stay those of
-        // `opt.fuse`
+        // state 0 bound on the host), then (unless `opt.fuse` fixes it) its
+        // tile width, timed over a sample of states run together as the batch
+        // runs them; measurement records are left out of the timed circuit,
+        // and the low-qubit choice stays that of `opt.fuse`
         std::vector<qsim_gate> timed;
         timed.reserve(in.ng);
         for (size_t i = 0; i < in.ng; i++)
@@ -183,11 +185,20 @@ int setup_group(Group &G, const qsim_batch_group &in, int dtype, const qsim_batc
                             GateInputs{in.mats, in.mats ? in.n_mats : 0, param ? in.params : nullptr,
                                        param ? size_t(in.n_params) : 0},
                             fo, &w, &ns);
-        G.tune_seconds = now_seconds() - t0;
         if (rc) return rc;
-        if (fo) tuned = *fo;
+        tuned = *fo;
         tuned.level = 5;
         tuned.max_width = w;
+        if (!(opt.fuse.level > 0 && opt.fuse.tile_qubits > 0) && !std::getenv("QSIM_TILE_QUBITS")) {
+            int t = tuned.tile_qubits;
+            rc = tune_tile_batch(in.n, dtype, timed.data(), timed.size(),
+                                 GateInputs{in.mats, in.mats ? in.n_mats : 0, param ? in.params : nullptr,
+                                            param ? size_t(in.n_params) : 0},
+                                 tuned, uint32_t(in.n_states), &t);
+            if (rc) return rc;
+            tuned.tile_qubits = t;
+        }
+        G.tune_seconds = now_seconds() - t0;
         fo = &tuned;
         G.tuned_width = w;
     }

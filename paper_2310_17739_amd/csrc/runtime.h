@@ -60,9 +60,17 @@ int validate_plan(int n, int dtype, const Compiled &c);
 // otherwise; writes the fastest width and its time per input gate.
 int tune_width(int n, int dtype, const qsim_gate *g, size_t ng, const GateInputs &in,
                const qsim_fuse_opts *base, int *best_w, double *best_ns);
+// Time tile widths 12 and 13 for a batch group's template (the other options
+// from `base`, fusion width included) over a sample of up to `nstates` states
+// run together, as the batch runs them; writes the faster width (base's tile
+// width for groups whose states fit one tile, which are not timed).
+int tune_tile_batch(int n, int dtype, const qsim_gate *g, size_t ng, const GateInputs &in,
+                    const qsim_fuse_opts &base, uint32_t nstates, int *best_t);
 int upload_plan(DeviceTables *dt, int dtype, const PackedPlan &plan, hipStream_t st);
 void free_tables(DeviceTables *dt);
+// (sstride, nstates: the same passes over nstates states laid out every
+// sstride elements, all with the plan's coefficients)
 int enqueue_passes(const Compiled &c, const DeviceTables &dt, int dtype, void *state,
-                   hipStream_t st, bool init_zero_first);
+                   hipStream_t st, bool init_zero_first, uint64_t sstride = 0, uint32_t nstates = 1);
 
 }  // namespace qs

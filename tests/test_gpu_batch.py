@@ -163,8 +163,10 @@ def test_alone_equals_in_batch_and_graph_replays(Q):
 
 def test_autotuned_batch_uses_tuned_width(Q):
     """With autotune, each group's fusion width is timed (2..5 for complex64)
-    on its template with the first state's angles, and the group is compiled
-    with the fastest; results still match the oracle."""
+    on its template with the first state's angles, then the tile width of a
+    group whose states need several tiles (12 or 13 qubits, timed over its
+    states run together); the group is compiled with the fastest; results
+    still match the oracle."""
     groups, want = [], []
     for w in (11, 16):
         rng = np.random.default_rng(100 + w)
@@ -185,6 +187,8 @@ def test_autotuned_batch_uses_tuned_width(Q):
     for gi, (w, g, H, th) in enumerate(want):
         st = b.qsim_batch_group_stats(gi)
         assert 2 <= st["tuned_width"] <= 5 and st["max_width"] == st["tuned_width"]
+        # a 14-qubit complex64 state is one tile; wider ones are tuned
+        assert st["tile_qubits"] == w if w <= 14 else st["tile_qubits"] in (12, 13)
         res = b.qsim_batch_results(gi)
         for s in range(3):
             psi, _, _ = oracle.run(w, g, params=th[s])
