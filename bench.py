@@ -487,7 +487,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy five times (a known byte count for "
                          "scaling memory counters)")
-    ap.add_argument("--forms", default="batched,served,mma,wide",
+    ap.add_argument("--forms", default="trajectories,batched,served,mma,wide",
                     help="comma list of extra forms to run: trajectories,batched,served,mma,wide "
                          "(or 'all'; '' or --no-forms for none)")
     ap.add_argument("--no-forms", action="store_true")
