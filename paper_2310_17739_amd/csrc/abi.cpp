@@ -109,10 +109,16 @@ void default_configs(int n, int dtype, const qsim_fuse_opts *opt, FuseConfig *fc
     if (pc->tile_qubits > n) pc->tile_qubits = n;
     pc->low_qubits = std::max(0, std::min(pc->low_qubits, pc->tile_qubits - 1));
     // LDS behind the tile (and its reduction scratch) for a pass's records and
-    // coefficients: at most 16 KiB, and what the tile leaves
+    // coefficients: as much as fits without lowering the number of workgroups
+    // a CU holds at once, which the tile's LDS and the tile kernel's
+    // registers set (two workgroups; four for complex64 tiles of 256
+    // threads).  QSIM_META_BUDGET caps it.
     const size_t tile_bytes = (size_t(1) << pc->tile_qubits) * elem_bytes(dtype) + qk::kTileRedBytes;
-    const size_t room = qk::max_lds_bytes() > tile_bytes ? qk::max_lds_bytes() - tile_bytes : 0;
-    pc->meta_budget = std::min(room, size_t(std::max(1024, env_int("QSIM_META_BUDGET", 16 * 1024))));
+    const size_t lds = qk::max_lds_bytes();
+    const size_t by_regs = (dtype == QSIM_C64 && pc->threads == 256) ? 4 : 2;
+    const size_t per_cu = std::max<size_t>(1, std::min(tile_bytes <= lds ? lds / tile_bytes : 0, by_regs));
+    const size_t room = lds / per_cu > tile_bytes ? lds / per_cu - tile_bytes : 0;
+    pc->meta_budget = std::min(room, size_t(std::max(1024, env_int("QSIM_META_BUDGET", 1 << 30))));
 }
 
 // The XCD-order qubits of a tiled pass: distinct qubits outside the tile.
