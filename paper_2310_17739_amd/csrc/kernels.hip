@@ -506,24 +506,41 @@ __device__ __forceinline__ uint64_t deposit(uint64_t x, uint64_t m) {
 
 // Measurement, assertion and reset inside a resident program (t == n, so the
 // LDS index is the amplitude index).  Returns 0 or a negative status.
-template <typename T, int TNT>
+// Thread tid holds the elements j = tid + i * TNT (i < E; with E = 1 and
+// t < log2 TNT only the first 2^t threads); the fold is linear, so element j
+// sits at slot sw(tid) ^ sw(i * TNT) and its partner j ^ 2^q at that slot
+// ^ sw(2^q).  The sums over j run in ascending i on every thread, then over
+// the threads in fixed order.
+template <typename T, int LE, int TNT>
 __device__ int lds_measure(int t, const OpRec &op, const MeasArgs &ma, uint32_t b) {
     using L = LdsTile<T>;
+    constexpr int E = 1 << LE;
+    constexpr int LOGT = (TNT == 512) ? 9 : 8;
     const int q = op.pos[0];
     const int slot = int(op.coef);
-    const int TN = 1 << t;
+    const int tid = threadIdx.x;
+    const bool active = (E > 1) || (tid < (1 << t));
+    const uint32_t stid = uint32_t(sw<T>(tid)) << L::LOGE;
+    auto addr = [&](int i) { return stid ^ (uint32_t(sw<T>(i * TNT)) << L::LOGE); };
+    auto bit = [&](int i) { return q < LOGT ? (tid >> q) & 1 : (i >> (q - LOGT)) & 1; };
     double w[2] = {0.0, 0.0};
-    for (int j = threadIdx.x; j < TN; j += TNT) w[(j >> q) & 1] += norm2(L::at(j));
+#pragma unroll
+    for (int i = 0; i < E; i++)
+        if (active) w[bit(i)] += norm2(L::ld(addr(i)));
     block_sum_in<2, TNT / 64>(w, L::red(t));
     const double P0 = w[0], P1 = w[1];
     if (op.kind == qs::DEVOP_RESET) {
         if (P1 == 0.0) return 0;
         if (P0 != 0.0) return QSIM_E_NOT_DEFINITE;
-        const int half = TN >> 1;
-        for (int g = threadIdx.x; g < half; g += TNT) {
-            const int lo = ((g >> q) << (q + 1)) | (g & ((1 << q) - 1));
-            L::set(lo, L::at(lo | (1 << q)));
-            L::set(lo | (1 << q), Cx<T>{T(0), T(0)});
+        // each pair (j, j | 2^q) moved by the thread that holds j
+        const uint32_t dq = uint32_t(sw<T>(1 << q)) << L::LOGE;
+#pragma unroll
+        for (int i = 0; i < E; i++) {
+            if (active && bit(i) == 0) {
+                const uint32_t a = addr(i);
+                L::st(a, L::ld(a ^ dq));
+                L::st(a ^ dq, Cx<T>{T(0), T(0)});
+            }
         }
         return 0;
     }
@@ -545,11 +562,14 @@ __device__ int lds_measure(int t, const OpRec &op, const MeasArgs &ma, uint32_t 
         ma.outcomes[idx] = o;
         ma.probs[idx] = kept / (P0 + P1);
     }
-    for (int j = threadIdx.x; j < TN; j += TNT) {
-        Cx<T> a = L::at(j);
-        if (((j >> q) & 1) == o) { a.re *= scale; a.im *= scale; }
-        else a = Cx<T>{T(0), T(0)};
-        L::set(j, a);
+#pragma unroll
+    for (int i = 0; i < E; i++) {
+        if (active) {
+            Cx<T> a = L::ld(addr(i));
+            if (bit(i) == o) { a.re *= scale; a.im *= scale; }
+            else a = Cx<T>{T(0), T(0)};
+            L::st(addr(i), a);
+        }
     }
     return 0;
 }
@@ -701,7 +721,7 @@ __global__ void __launch_bounds__(TNT) k_tile(Cx<T> *__restrict__ state, uint64_
         } else {
             // the same on every lane: keeps the loop (and the record
             // addresses) uniform
-            status = __builtin_amdgcn_readfirstlane(lds_measure<T, TNT>(ta.t, op, ma, b));
+            status = __builtin_amdgcn_readfirstlane(lds_measure<T, LE, TNT>(ta.t, op, ma, b));
         }
         if (i + 1 < iend) {
             op = decode_op(rec_at + uint32_t(i + 1) * uint32_t(sizeof(DevOp)));
