@@ -360,7 +360,10 @@ __device__ __forceinline__ void apply_lds(int t, const OpRec &op, uint32_t cfb, 
     } else {
         constexpr int LOGT = (TNT == 512) ? 9 : 8;
         constexpr int LG = LE - K;                                  // log2 groups per thread
-        constexpr int LB = (LG < 4 - K) ? LG : (K >= 4 ? 0 : 4 - K);   // log2 groups per batch
+        // log2 amplitudes per batch: 16, or 32 for whole 14-qubit complex64
+        // states (one workgroup per CU, so registers are plentiful)
+        constexpr int MB = (sizeof(T) == 4 && LE == 5 && TNT == 512) ? 5 : 4;
+        constexpr int LB = (LG < MB - K) ? LG : (K >= MB ? 0 : MB - K);   // log2 groups per batch
         // offsets of the basis groups 2^b * TNT
         uint32_t gb[LG];
 #pragma unroll
