@@ -1065,6 +1065,12 @@ __global__ void __launch_bounds__(NT) k_dense_mfma(Cx<float> *__restrict__ state
     int p[KQ];
 #pragma unroll
     for (int j = 0; j < KQ; j++) p[j] = op.pos[j];
+    // the operator's coefficients, staged in LDS once per workgroup: the A
+    // operands below read each of them on many lanes
+    __shared__ Cx<float> cs[D * D];
+    const int nterm = __builtin_popcount(op.present);
+    for (int x = int(threadIdx.x); x < nterm * D; x += NT) cs[x] = c[x];
+    __syncthreads();
     // A operand of every step and row block: real embedding of M[r][col],
     // M[r][col] = d_m[r] for the XOR shift m = r ^ col when present
     float a[NRB][D];
@@ -1078,7 +1084,7 @@ __global__ void __launch_bounds__(NT) k_dense_mfma(Cx<float> *__restrict__ state
             float re = 0.f, im = 0.f;
             if ((op.present >> m) & 1u) {
                 const int t = __builtin_popcount(op.present & ((1u << m) - 1u));
-                const Cx<float> v = c[t * D + r];
+                const Cx<float> v = cs[t * D + r];
                 re = v.re;
                 im = v.im;
             }
