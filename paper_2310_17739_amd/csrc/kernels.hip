@@ -511,23 +511,35 @@ __device__ __forceinline__ uint64_t deposit(uint64_t x, uint64_t m) {
 // LDS index is the amplitude index).  Returns 0 or a negative status.
 // Thread tid holds the elements j = tid + i * TNT (i < E; with E = 1 and
 // t < log2 TNT only the first 2^t threads); the fold is linear, so element j
-// sits at slot sw(tid) ^ sw(i * TNT) and its partner j ^ 2^q at that slot
-// ^ sw(2^q).  The sums over j run in ascending i on every thread, then over
-// the threads in fixed order.
+// sits at slot sw(tid) ^ sw(i * TNT), with sw(i * TNT) the XOR of the
+// constants sw(TNT << c) over the set bits c of i, and its partner j ^ 2^q at
+// that slot ^ sw(2^q).  The sums over j run in ascending i on every thread,
+// then over the threads in fixed order.  The loops stay rolled except for
+// whole 14-qubit complex64 states: this code is compiled into every tile
+// kernel, whose registers it must not raise.
 template <typename T, int LE, int TNT>
 __device__ int lds_measure(int t, const OpRec &op, const MeasArgs &ma, uint32_t b) {
     using L = LdsTile<T>;
     constexpr int E = 1 << LE;
     constexpr int LOGT = (TNT == 512) ? 9 : 8;
+    // unrolled only where one workgroup fills a CU (whole 14-qubit complex64
+    // states) and registers are plentiful
+    constexpr int UNR = (LE >= 5) ? E : 1;
     const int q = op.pos[0];
     const int slot = int(op.coef);
     const int tid = threadIdx.x;
     const bool active = (E > 1) || (tid < (1 << t));
     const uint32_t stid = uint32_t(sw<T>(tid)) << L::LOGE;
-    auto addr = [&](int i) { return stid ^ (uint32_t(sw<T>(i * TNT)) << L::LOGE); };
+    auto addr = [&](int i) {
+        uint32_t a = stid;
+#pragma unroll
+        for (int c = 0; c < LE; c++)
+            if ((i >> c) & 1) a ^= uint32_t(sw<T>(TNT << c)) << L::LOGE;
+        return a;
+    };
     auto bit = [&](int i) { return q < LOGT ? (tid >> q) & 1 : (i >> (q - LOGT)) & 1; };
     double w[2] = {0.0, 0.0};
-#pragma unroll
+#pragma unroll UNR
     for (int i = 0; i < E; i++)
         if (active) w[bit(i)] += norm2(L::ld(addr(i)));
     block_sum_in<2, TNT / 64>(w, L::red(t));
@@ -537,7 +549,7 @@ __device__ int lds_measure(int t, const OpRec &op, const MeasArgs &ma, uint32_t 
         if (P0 != 0.0) return QSIM_E_NOT_DEFINITE;
         // each pair (j, j | 2^q) moved by the thread that holds j
         const uint32_t dq = uint32_t(sw<T>(1 << q)) << L::LOGE;
-#pragma unroll
+#pragma unroll UNR
         for (int i = 0; i < E; i++) {
             if (active && bit(i) == 0) {
                 const uint32_t a = addr(i);
@@ -565,7 +577,7 @@ __device__ int lds_measure(int t, const OpRec &op, const MeasArgs &ma, uint32_t 
         ma.outcomes[idx] = o;
         ma.probs[idx] = kept / (P0 + P1);
     }
-#pragma unroll
+#pragma unroll UNR
     for (int i = 0; i < E; i++) {
         if (active) {
             Cx<T> a = L::ld(addr(i));
