@@ -35,9 +35,9 @@ LDS_PEAK_GBS = 128 * 256 * 2.4
 # The figures hold for the kernel sources with the hash below (see
 # kernel_source_hash); for any other source the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "kernels_sha256_16": "72f9dd2130a3aa8e",
-    "complex128": (16653.3 * 2.0 + 32781.7) * 1024,
-    "complex64": (8389.0 * 2.0 + 16387.4) * 1024,
+    "kernels_sha256_16": "bba51b7913e1dfc5",
+    "complex128": (16658.9 * 2.0 + 32781.0) * 1024,
+    "complex64": (8385.7 * 2.0 + 16386.4) * 1024,
 }
 
 
