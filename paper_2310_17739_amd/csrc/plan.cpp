@@ -12,7 +12,13 @@
 //
 // Operators commute when they touch disjoint qubits, so a pass may take an
 // operator from further down the list as long as no skipped operator before
-// it shares one of its qubits.
+// it shares one of its qubits.  Operators that share qubits may commute as
+// well: two functions of one Pauli string each (a I + b P, the fused
+// exponentials of the benchmark circuits) commute exactly when their strings
+// do, and diagonal operators commute with each other and with any such
+// operator whose string moves none of their qubits.  The planner lets an
+// operator pass skipped ones it commutes with in this sense (QSIM_PLAN_COMMUTE=0
+// turns it off).
 //
 // A qubit on which an operator is diagonal (no XOR shift of it moves that
 // qubit: Z letters of a Pauli string, the phase of a controlled phase) need
@@ -22,10 +28,82 @@
 // against the tile's width.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "host.h"
 
 namespace qs {
+
+namespace {
+
+// Commutation class of an operator: a function a I + b X^x Z^z of one Pauli
+// string (x, z over the circuit's qubits), a diagonal, or neither.  Entries
+// are compared to 1e-13 of the operator's largest one.
+struct OpClass {
+    int kind = 0;   // 0 neither, 1 diagonal, 2 Pauli function
+    uint64_t q = 0, x = 0, z = 0;
+};
+
+OpClass op_class(const Op &o) {
+    OpClass c;
+    c.q = o.mask();
+    if (o.np > 0 || o.m.empty()) return c;
+    const int d = o.dim();
+    double mx = 0.0;
+    for (const cd &v : o.m) mx = std::max(mx, std::abs(v));
+    const double tol = 1e-13 * mx;
+    auto at = [&](int r, int col) { return o.m[size_t(r) * d + size_t(col)]; };
+    uint32_t present = 0;
+    for (int s = 0; s < d; s++)
+        for (int r = 0; r < d; r++)
+            if (std::abs(at(r, r ^ s)) > tol) { present |= 1u << s; break; }
+    if (present == 1u) {
+        c.kind = 1;
+        return c;
+    }
+    // at most the main diagonal (constant) and one shift X
+    const uint32_t others = present & ~1u;
+    if (__builtin_popcount(others) != 1) return c;
+    const int X = __builtin_ctz(others);
+    if (present & 1u)
+        for (int r = 1; r < d; r++)
+            if (std::abs(at(r, r) - at(0, 0)) > tol) return c;
+    // the shift's entries: a common value times the signs (-1)^popcount(r & z)
+    const cd d0 = at(0, X);
+    int zl = 0;
+    for (int j = 0; j < o.k; j++) {
+        const cd v = at(1 << j, (1 << j) ^ X);
+        if (std::abs(v + d0) <= tol) zl |= 1 << j;
+        else if (std::abs(v - d0) > tol) return c;
+    }
+    for (int r = 0; r < d; r++) {
+        const double sg = (__builtin_popcount(r & zl) & 1) ? -1.0 : 1.0;
+        if (std::abs(at(r, r ^ X) - sg * d0) > tol) return c;
+    }
+    c.kind = 2;
+    for (int j = 0; j < o.k; j++) {
+        if ((X >> j) & 1) c.x |= uint64_t(1) << o.q[j];
+        if ((zl >> j) & 1) c.z |= uint64_t(1) << o.q[j];
+    }
+    return c;
+}
+
+bool commute(const OpClass &a, const OpClass &b) {
+    if (!(a.q & b.q)) return true;
+    if (a.kind == 2 && b.kind == 2)
+        return ((__builtin_popcountll(a.x & b.z) + __builtin_popcountll(a.z & b.x)) & 1) == 0;
+    if (a.kind == 1 && b.kind == 1) return true;
+    if (a.kind == 1 && b.kind == 2) return (b.x & a.q) == 0;
+    if (a.kind == 2 && b.kind == 1) return (a.x & b.q) == 0;
+    return false;
+}
+
+// Operators scanned after every qubit is blocked by a skipped operator: only
+// commuting ones can still join the pass, and a longer tail finds none more
+// on the benchmark circuits.
+constexpr int kCommuteTail = 64;
+
+}  // namespace
 
 void plan_passes(int n, const Lowered &L, const std::vector<uint32_t> &meta_bytes,
                  const std::vector<uint64_t> &need, const PlanConfig &cfg, std::vector<Pass> *passes) {
@@ -120,6 +198,14 @@ void plan_passes(int n, const Lowered &L, const std::vector<uint32_t> &meta_byte
         return;
     }
 
+    const char *cv = std::getenv("QSIM_PLAN_COMMUTE");
+    const bool use_commute = !(cv && *cv && std::atoi(cv) == 0);
+    std::vector<OpClass> cls;
+    if (use_commute) {
+        cls.resize(size_t(N));
+        for (int i = 0; i < N; i++) cls[size_t(i)] = op_class(ops[i]);
+    }
+    std::vector<OpClass> skipped;   // classes of the operators a pass skipped, in order
     // doubly linked list of pending operators of one epoch
     std::vector<int> nxt(N + 1), prv(N + 1);
     const int head = N;
@@ -142,21 +228,36 @@ void plan_passes(int n, const Lowered &L, const std::vector<uint32_t> &meta_byte
             }
             uint64_t T = low, blocked = 0;
             std::vector<int> sel;
+            skipped.clear();
             size_t meta = 0;
-            int scanned = 0;
+            int scanned = 0, all_blocked_at = -1;
             for (int i = nxt[head]; i != head && scanned < cfg.window; i = nxt[i], scanned++) {
                 const uint64_t qm = ops[i].mask();
-                if ((qm & blocked) || ops[i].k > cfg.max_tile_k ||
-                    (!sel.empty() && meta + meta_bytes[i] > cfg.meta_budget)) {
-                    blocked |= qm;
-                } else if (__builtin_popcountll(T | need[i]) <= t) {
+                // may the operator run before every skipped one?
+                bool free = !(qm & blocked);
+                if (!free && use_commute) {
+                    free = true;
+                    const OpClass &ci = cls[size_t(i)];
+                    for (const OpClass &s : skipped)
+                        if (!commute(s, ci)) {
+                            free = false;
+                            break;
+                        }
+                }
+                if (free && ops[i].k <= cfg.max_tile_k && (sel.empty() || meta + meta_bytes[i] <= cfg.meta_budget) &&
+                    __builtin_popcountll(T | need[i]) <= t) {
                     T |= need[i];
                     sel.push_back(i);
                     meta += meta_bytes[i];
                 } else {
                     blocked |= qm;
+                    if (use_commute) skipped.push_back(cls[size_t(i)]);
                 }
-                if (blocked == all) break;
+                if (blocked == all) {
+                    if (!use_commute) break;
+                    if (all_blocked_at < 0) all_blocked_at = scanned;
+                    else if (scanned - all_blocked_at >= kCommuteTail) break;
+                }
             }
             for (int i : sel) {
                 nxt[prv[i]] = nxt[i];
