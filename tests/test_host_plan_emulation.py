@@ -25,7 +25,7 @@ def check(got, want, rel=1e-12):
 
 
 @pytest.mark.parametrize("dtype", ["complex128", "complex64"])
-@pytest.mark.parametrize("n,tile", [(8, 5), (12, 8), (15, 9), (16, 12)])
+@pytest.mark.parametrize("n,tile", [(8, 5), (12, 8), (14, None), (15, 9), (16, 12)])
 @pytest.mark.parametrize("gen", ["all_kinds", "pauli", "diagonal"])
 def test_packed_plan_equals_oracle(dtype, n, tile, gen):
     if gen == "all_kinds":
