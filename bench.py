@@ -36,8 +36,8 @@ LDS_PEAK_GBS = 128 * 256 * 2.4
 # kernel_source_hash); for any other source the traffic is reported as null.
 MEASURED_TRAFFIC = {
     "kernels_sha256_16": "bba51b7913e1dfc5",
-    "complex128": (16658.9 * 2.0 + 32781.0) * 1024,
-    "complex64": (8385.7 * 2.0 + 16386.4) * 1024,
+    "complex128": (16661.4 * 2.0 + 32782.9) * 1024,
+    "complex64": (8386.2 * 2.0 + 16386.7) * 1024,
 }
 
 
