@@ -192,12 +192,13 @@ def run_trajectories(qsim, W, ntraj=1024, rounds=500):
     # The 128 KiB state stays in one workgroup's LDS for the whole program, so
     # LDS bounds this form: every fused operator reads and writes the state
     # there once, and each measurement or reset record reads it and rewrites
-    # it (counted as one more read and write).
-    lds_bytes = ntraj * (info["fused_ops"] + 4 * rounds) * 2 * 8 * (1 << 14)
+    # it (counted as one more read and write; a reset that follows a
+    # measurement of its qubit runs inside that measurement's record).
+    lds_bytes = ntraj * (info["fused_ops"] + info["records"]) * 2 * 8 * (1 << 14)
     return {"workload": f"{ntraj} trajectories x {rounds} rounds, 14 qubits, complex64",
             "seconds": dt, "trajectory_rounds_per_s": ntraj * rounds / dt,
             "input_gates_per_s": ntraj * len(g) / dt, "passes": info["passes"],
-            "fused_ops_per_trajectory": info["fused_ops"],
+            "fused_ops_per_trajectory": info["fused_ops"], "records_per_trajectory": info["records"],
             "lds": {"bytes": lds_bytes, "achieved_GBps": lds_bytes / dt / 1e9, "peak_GBps": LDS_PEAK_GBS,
                     "frac": lds_bytes / dt / 1e9 / LDS_PEAK_GBS},
             "failed": int((res["status"] != 0).sum()),

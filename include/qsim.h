@@ -317,6 +317,10 @@ typedef struct qsim_batch_info {
     int64_t coef_bytes;
     double compile_seconds;  /* includes tune_seconds */
     double tune_seconds;     /* time spent by the autotuner (0 without it) */
+    int64_t records;         /* summed over groups: measurement, assertion and reset
+                                records run per state, after a reset that follows a
+                                record of its qubit with no gate between has been
+                                joined to it or dropped (QSIM_FOLD_RESETS=0 keeps all) */
 } qsim_batch_info;
 
 /* Compile every group once (lowering, fusion, plan; angle-dependent

@@ -223,7 +223,9 @@ int validate_plan(int n, int dtype, const Compiled &c) {
             continue;
         }
         if (pi.kind == Pass::MEASURE) {
-            if (p.pass_begin[i] != p.pass_begin[i + 1] || pi.meas.q < 0 || pi.meas.q >= n) return QSIM_E_ARG;
+            if (p.pass_begin[i] != p.pass_begin[i + 1] || pi.meas.q < 0 || pi.meas.q >= n ||
+                !devop_is_record(pi.meas.kind))
+                return QSIM_E_ARG;
             continue;
         }
         if (!pi.strided) {
@@ -280,7 +282,7 @@ int validate_plan(int n, int dtype, const Compiled &c) {
             const DevOp &o = p.ops[j];
             if (o.kind != DEVOP_MAT) {
                 // measurement records run only inside resident (whole-state) passes
-                if (pi.strided || pi.ta.t != n || o.pos[0] >= n || o.kind > DEVOP_RESET) return QSIM_E_ARG;
+                if (pi.strided || pi.ta.t != n || o.pos[0] >= n || !devop_is_record(o.kind)) return QSIM_E_ARG;
                 continue;
             }
             // tiled passes may hold operators with block qubits (kx > 0),
@@ -416,6 +418,7 @@ int compile_program(int n, int dtype, const qsim_gate *g, size_t ng, const GateI
     s.input_gates = L.input_gates;
     for (int l = 0; l < 6; l++) s.ops_after[l] = counts[l];
     s.fused_ops = int64_t(L.ops.size());
+    out->records = int64_t(L.meas.size());
     s.passes = int64_t(passes.size());
     s.terms = out->plan.terms;
     s.bytes_moved = int64_t(passes.size()) * 2 * (int64_t(1) << n) * int64_t(elem_bytes(dtype));

@@ -412,6 +412,7 @@ int qsim_batch_create(const qsim_batch_group *groups, int n_groups, const qsim_b
                 b->info.input_gates += G.c.stats.input_gates * G.nstates;
                 b->info.fused_ops += G.c.stats.fused_ops;
                 b->info.passes += G.c.stats.passes;
+                b->info.records += G.c.records;
                 b->info.tune_seconds += G.tune_seconds;
                 b->info.state_bytes += int64_t(G.nstates) * int64_t(G.sstride * elem_bytes(o.dtype));
                 b->info.coef_bytes += G.coef_bytes;

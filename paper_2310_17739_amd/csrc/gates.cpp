@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 
 #include <rocprofiler-sdk-roctx/roctx.h>
 
@@ -278,11 +279,23 @@ int lower(int n, const qsim_gate *g, size_t ng, const GateInputs &in, bool keep_
     out->ops.reserve(ng);
     out->op_epoch.reserve(ng);
     int epoch = 0;
+    // Records out->meas[run_begin ..] follow each other with no operator or
+    // barrier between them.  Non-unitary steps on different qubits commute,
+    // and after a measurement, an assertion or a reset the qubit is definite,
+    // so a reset that meets an earlier record of its qubit in the same run
+    // either joins a measurement (one record that collapses the state and
+    // moves the outcome to |0>) or is a no-op and is dropped; each such
+    // reset saves a reduction and a rewrite of the state (QSIM_FOLD_RESETS=0
+    // keeps every record as written).
+    const char *fv = std::getenv("QSIM_FOLD_RESETS");
+    const bool fold_resets = !(fv && *fv && std::atoi(fv) == 0);
+    size_t run_begin = 0;
     std::vector<cd> m, m2;
     for (size_t i = 0; i < ng; i++) {
         const qsim_gate &gi = g[i];
         if (gi.kind == QSIM_G_BARRIER) {
             epoch++;
+            run_begin = out->meas.size();
             continue;
         }
         if (gi.kind == QSIM_G_MEASURE || gi.kind == QSIM_G_RESET || gi.kind == QSIM_G_ASSERT0) {
@@ -290,6 +303,17 @@ int lower(int n, const qsim_gate *g, size_t ng, const GateInputs &in, bool keep_
             if (gi.nq != 1) return QSIM_E_ARG;
             if (gi.q[0] < 0 || gi.q[0] >= n) return QSIM_E_QUBIT;
             if (gi.kind != QSIM_G_RESET && gi.slot < 0) return QSIM_E_ARG;
+            if (gi.kind == QSIM_G_RESET && fold_resets) {
+                bool folded = false;
+                for (size_t j = out->meas.size(); j > run_begin; j--) {
+                    MeasRec &prev = out->meas[j - 1];
+                    if (prev.q != gi.q[0]) continue;
+                    if (prev.kind == DEVOP_MEASURE) prev.kind = DEVOP_MEASURE_RESET;
+                    folded = true;
+                    break;
+                }
+                if (folded) continue;
+            }
             MeasRec r;
             r.epoch = epoch;
             r.kind = gi.kind == QSIM_G_MEASURE ? DEVOP_MEASURE
@@ -356,6 +380,7 @@ int lower(int n, const qsim_gate *g, size_t ng, const GateInputs &in, bool keep_
         out->ops.push_back(std::move(op));
         out->op_epoch.push_back(epoch);
         out->input_gates++;
+        run_begin = out->meas.size();
     }
     out->n_epochs = epoch + 1;
     return QSIM_OK;

@@ -46,7 +46,7 @@ struct Op {
 // operators of epoch `epoch` and before those of epoch + 1.
 struct MeasRec {
     int epoch = 0;
-    int kind = 0;   // DEVOP_MEASURE, DEVOP_ASSERT0 or DEVOP_RESET
+    int kind = 0;   // DEVOP_MEASURE, DEVOP_ASSERT0, DEVOP_RESET or DEVOP_MEASURE_RESET
     int q = 0;
     int slot = 0;
 };
@@ -210,9 +210,13 @@ enum { DEVOP_MAT = 0, DEVOP_MEASURE = 1, DEVOP_ASSERT0 = 2, DEVOP_RESET = 3,
                           // shifts, k = kRegBits, coefficients 2^k per shift, kx / xq block qubits
        DEVOP_SWAP = 5,    // pos[0] = lane bit (4 or 5), pos[1] = register bit: exchange them
        DEVOP_XPOSE = 6,   // LDS re-layout; bytes 0..13 = canonical bit per position before,
-       DEVOP_XPOSE2 = 7   // and, in the record that follows, after
+       DEVOP_XPOSE2 = 7,  // and, in the record that follows, after
+       DEVOP_MEASURE_RESET = 8   // a measurement followed by a reset of the same qubit
 };
 inline bool devop_is_mat(int kind) { return kind == DEVOP_MAT || kind == DEVOP_RMAT; }
+inline bool devop_is_record(int kind) {
+    return kind == DEVOP_MEASURE || kind == DEVOP_ASSERT0 || kind == DEVOP_RESET || kind == DEVOP_MEASURE_RESET;
+}
 
 struct PackedPlan {
     std::vector<DevOp> ops;             // in pass order

@@ -507,9 +507,9 @@ __device__ __forceinline__ uint64_t deposit(uint64_t x, uint64_t m) {
     return r;
 }
 
-// Measurement, assertion and reset inside a resident program (t == n, so the
-// LDS index is the amplitude index).  Returns 0 or a negative status.
-// Thread tid holds the elements j = tid + i * TNT (i < E; with E = 1 and
+// Measurement, assertion, reset, and measurement then reset, inside a
+// resident program (t == n, so the LDS index is the amplitude index).
+// Returns 0 or a negative status.  Thread tid holds the elements j = tid + i * TNT (i < E; with E = 1 and
 // t < log2 TNT only the first 2^t threads); the fold is linear, so element j
 // sits at slot sw(tid) ^ sw(i * TNT), with sw(i * TNT) the XOR of the
 // constants sw(TNT << c) over the set bits c of i, and its partner j ^ 2^q at
@@ -544,19 +544,26 @@ __device__ int lds_measure(int t, const OpRec &op, const MeasArgs &ma, uint32_t 
         if (active) w[bit(i)] += norm2(L::ld(addr(i)));
     block_sum_in<2, TNT / 64>(w, L::red(t));
     const double P0 = w[0], P1 = w[1];
-    if (op.kind == qs::DEVOP_RESET) {
-        if (P1 == 0.0) return 0;
-        if (P0 != 0.0) return QSIM_E_NOT_DEFINITE;
-        // each pair (j, j | 2^q) moved by the thread that holds j
-        const uint32_t dq = uint32_t(sw<T>(1 << q)) << L::LOGE;
+    // Each pair (j, j | 2^q) rewritten by the thread that holds j: j takes
+    // s times the amplitude at j ^ src, j | 2^q becomes 0.
+    const uint32_t dq = uint32_t(sw<T>(1 << q)) << L::LOGE;
+    auto to_zero = [&](uint32_t src, T s) {
 #pragma unroll UNR
         for (int i = 0; i < E; i++) {
             if (active && bit(i) == 0) {
                 const uint32_t a = addr(i);
-                L::st(a, L::ld(a ^ dq));
+                Cx<T> c = L::ld(a ^ src);
+                c.re *= s;
+                c.im *= s;
+                L::st(a, c);
                 L::st(a ^ dq, Cx<T>{T(0), T(0)});
             }
         }
+    };
+    if (op.kind == qs::DEVOP_RESET) {
+        if (P1 == 0.0) return 0;
+        if (P0 != 0.0) return QSIM_E_NOT_DEFINITE;
+        to_zero(dq, T(1));
         return 0;
     }
     int o;
@@ -576,6 +583,11 @@ __device__ int lds_measure(int t, const OpRec &op, const MeasArgs &ma, uint32_t 
     if (threadIdx.x == 0) {
         ma.outcomes[idx] = o;
         ma.probs[idx] = kept / (P0 + P1);
+    }
+    if (op.kind == qs::DEVOP_MEASURE_RESET) {
+        // collapse onto outcome o and move it to |0> in one rewrite
+        to_zero(o ? dq : 0u, scale);
+        return 0;
     }
 #pragma unroll UNR
     for (int i = 0; i < E; i++) {
@@ -1313,10 +1325,10 @@ __global__ void __launch_bounds__(NT) k_finish(const double *__restrict__ partia
 }
 
 // ------------------------------------------------- batched measurement
-// Measurement, assertion or reset of qubit q in every state of a batch whose
-// state does not fit one tile: P0, P1 come from a marginal reduction
-// (p01[2b], p01[2b+1]); every thread takes the same decision from them and
-// updates its amplitude pairs (x, x | 2^q).
+// Measurement, assertion, reset, or measurement then reset, of qubit q in
+// every state of a batch whose state does not fit one tile: P0, P1 come from
+// a marginal reduction (p01[2b], p01[2b+1]); every thread takes the same
+// decision from them and updates its amplitude pairs (x, x | 2^q).
 template <typename T>
 __global__ void __launch_bounds__(NT) k_decide(Cx<T> *__restrict__ state, uint64_t sstride, int n,
                                                int q, int kind, int slot,
@@ -1326,6 +1338,7 @@ __global__ void __launch_bounds__(NT) k_decide(Cx<T> *__restrict__ state, uint64
     const double P0 = p01[2 * b], P1 = p01[2 * b + 1];
     int o = 0, fail = 0;
     bool swap = false, touch = true;
+    const bool to_zero = kind == qs::DEVOP_MEASURE_RESET;   // the outcome then moves to |0>
     double kept = 1.0;
     const size_t idx = size_t(b) * ma.nslots + slot;
     if (kind == qs::DEVOP_RESET) {
@@ -1364,6 +1377,7 @@ __global__ void __launch_bounds__(NT) k_decide(Cx<T> *__restrict__ state, uint64
         Cx<T> n0, n1 = Cx<T>{T(0), T(0)};
         if (swap) n0 = a1;
         else if (o == 0) n0 = Cx<T>{a0.re * scale, a0.im * scale};
+        else if (to_zero) n0 = Cx<T>{a1.re * scale, a1.im * scale};
         else { n0 = Cx<T>{T(0), T(0)}; n1 = Cx<T>{a1.re * scale, a1.im * scale}; }
         st[x0] = n0;
         st[x1] = n1;

@@ -131,9 +131,9 @@ int launch_sweep(int dtype, void *state, uint64_t sstride, uint32_t nstates, int
                  const qs::DevOp &op, const void *coefs, hipStream_t st, uint64_t cstride = 0,
                  const int32_t *status = nullptr);
 
-// Measurement / assertion / reset of qubit q in every state of a batch from
-// per-state weights p01[2b], p01[2b+1] (a marginal reduction), decided on
-// the device (kind: qs::DEVOP_*).
+// Measurement / assertion / reset / measurement-then-reset of qubit q in
+// every state of a batch from per-state weights p01[2b], p01[2b+1] (a
+// marginal reduction), decided on the device (kind: qs::DEVOP_*).
 int launch_decide(int dtype, void *state, uint64_t sstride, uint32_t nstates, int n, int q,
                   int kind, int slot, const double *p01, const MeasArgs &ma, hipStream_t st);
 

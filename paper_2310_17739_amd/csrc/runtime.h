@@ -25,6 +25,7 @@ struct Compiled {
     std::vector<PassInfo> passes;
     qsim_apply_stats stats{};
     int64_t stats_reg_swaps = 0, stats_reg_xposes = 0;   // register-resident passes
+    int64_t records = 0;   // measurement, assertion and reset records after folding
 };
 
 // Device copies of a packed plan with a pinned staging buffer.

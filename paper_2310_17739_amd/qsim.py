@@ -152,7 +152,7 @@ class qsim_batch_opts(C.Structure):
 class qsim_batch_info(C.Structure):
     _fields_ = [("states", C.c_int64), ("input_gates", C.c_int64), ("fused_ops", C.c_int64),
                 ("passes", C.c_int64), ("state_bytes", C.c_int64), ("coef_bytes", C.c_int64),
-                ("compile_seconds", C.c_double), ("tune_seconds", C.c_double)]
+                ("compile_seconds", C.c_double), ("tune_seconds", C.c_double), ("records", C.c_int64)]
 
 
 _lib = _load()

@@ -87,6 +87,83 @@ def test_trajectories_tiled(Q, dtype):
     check_trajectories(Q, n, g, u, dtype, res, b, 1e-12 if dtype == "complex128" else 1e-5)
 
 
+def _record_runs_program(n, rounds, seed):
+    """Rounds of Ry rotations and a CNOT chain, each followed by record runs
+    that meet every reset-folding case: measure 0, measure 1, reset 0,
+    reset 1 (two measure-then-reset records); assert 2, reset 2 (the reset
+    is dropped); measure 3, reset 3, reset 3 (one record); measure 4, a gate,
+    reset 4 and measure 5, a barrier, reset 5 (nothing joins).  Returns
+    (gates, n_slots, measured slot mask, records per state with folding,
+    records as written)."""
+    rng = np.random.default_rng(seed)
+    recs, measured, slot = [], [], 0
+    for _ in range(rounds):
+        for q in range(n):
+            recs.append((W.KIND_RY, (q,), (rng.uniform(0, 2 * np.pi),)))
+        for q in range(n - 1):
+            recs.append((W.KIND_CX, (q, q + 1), ()))
+        recs += [(W.KIND_MEASURE, (0,), (), slot), (W.KIND_MEASURE, (1,), (), slot + 1),
+                 (W.KIND_RESET, (0,), ()), (W.KIND_RESET, (1,), ()),
+                 (W.KIND_ASSERT0, (2,), (), slot + 2), (W.KIND_RESET, (2,), ()),
+                 (W.KIND_MEASURE, (3,), (), slot + 3), (W.KIND_RESET, (3,), ()), (W.KIND_RESET, (3,), ()),
+                 (W.KIND_MEASURE, (4,), (), slot + 4), (W.KIND_H, (5,), ()), (W.KIND_RESET, (4,), ()),
+                 (W.KIND_MEASURE, (5,), (), slot + 5), (W.KIND_BARRIER, (5,), ()), (W.KIND_RESET, (5,), ())]
+        measured += [True, True, False, True, True, True]
+        slot += 6
+    return W.gates(recs), slot, np.array(measured), 8 * rounds, 13 * rounds
+
+
+@pytest.mark.parametrize("dtype,n,tile", [("complex128", 8, None), ("complex64", 8, None),
+                                          ("complex128", 15, 10), ("complex64", 15, 10)])
+def test_reset_folding(Q, dtype, n, tile, monkeypatch):
+    """A reset that follows a record of its qubit with no gate or barrier
+    between joins a measurement or is dropped (resident programs: one LDS
+    rewrite; wider states: one decision sweep).  Outcomes, probabilities
+    and states equal the oracle's for the same draws, and equal those of
+    the program run with every record as written."""
+    rounds, ntraj = (4, 32) if n <= 8 else (2, 3)
+    g, nslots, measured, n_fold, n_all = _record_runs_program(n, rounds, seed=21)
+    u = W.uniforms((ntraj, nslots), seed=22)
+    tol = 1e-12 if dtype == "complex128" else 1e-5
+    kw = {} if tile is None else {"tile_qubits": tile}
+    say("reset folding", dtype, n, tile)
+
+    def run(fold, forced=None):
+        monkeypatch.setenv("QSIM_FOLD_RESETS", "1" if fold else "0")
+        grp = {"n": n, "n_states": ntraj, "gates": g, "uniforms": u, "n_slots": nslots}
+        if forced is not None:
+            grp["forced"] = forced
+        b = Q.Batch([grp], dtype=dtype, **kw)
+        b.qsim_batch_run()
+        res = b.qsim_batch_results(0)
+        states = [b.qsim_batch_get_state(0, t) for t in range(ntraj)]
+        info = b.qsim_batch_info()
+        b.close()
+        return res, states, info
+
+    res, states, info = run(True)
+    assert info["records"] == n_fold and (res["status"] == 0).all()
+    for t in range(ntraj):
+        go = res["outcomes"][t]
+        psi, _, op = oracle.run(n, g, uniforms=u[t], forced=go, n_slots=nslots)
+        p0 = np.where(go == 0, op, 1 - op)
+        mism = measured & (np.where(u[t] < p0, 0, 1) != go)
+        if dtype == "complex128":
+            assert not mism.any(), (t, np.nonzero(mism))
+        else:
+            assert np.all(np.abs(u[t][mism] - p0[mism]) < 1e-5)
+        assert np.all(go[~measured] == 0)
+        np.testing.assert_allclose(res["probs"][t], op, atol=1e-12 if dtype == "complex128" else 2e-5)
+        assert oracle.infidelity(psi, states[t]) < tol
+    # the same program with every record as written, forced to the same outcomes
+    res2, states2, info2 = run(False, forced=res["outcomes"])
+    assert info2["records"] == n_all and (res2["status"] == 0).all()
+    assert np.array_equal(res2["outcomes"], res["outcomes"])
+    np.testing.assert_allclose(res2["probs"], res["probs"], atol=1e-12 if dtype == "complex128" else 2e-5)
+    for t in range(ntraj):
+        assert oracle.infidelity(states[t], states2[t]) < tol
+
+
 @pytest.mark.parametrize("n", [6, 15])
 def test_assertion_failure_marks_only_that_state(Q, n):
     """X then Ry(theta_b) on the ancilla, then ASSERT0: theta = 0 leaves the
