@@ -30,14 +30,15 @@ LDS_PEAK_GBS = 128 * 256 * 2.4
 
 # HBM bytes per launch of the tile kernel at 21 qubits, from two counter runs
 # of this benchmark (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE; KiB per
-# dispatch).  A plain 256 MiB device copy dispatch reads FETCH_SIZE = 131,085 KiB
-# and WRITE_SIZE = 262,144 KiB, so fetches scale by 2.0 and writes by 1.0.
+# dispatch).  A plain device copy dispatch of 128 MiB reads FETCH_SIZE =
+# 65,544 KiB and WRITE_SIZE = 131,073 KiB, so fetches scale by 2.0 and writes
+# by 1.0.
 # The figures hold for the kernel sources with the hash below (see
 # kernel_source_hash); for any other source the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "kernels_sha256_16": "bba51b7913e1dfc5",
-    "complex128": (16661.4 * 2.0 + 32782.9) * 1024,
-    "complex64": (8386.2 * 2.0 + 16386.7) * 1024,
+    "kernels_sha256_16": "ba57d9ffd67a8358",
+    "complex128": (16673.0 * 2.0 + 32783.2) * 1024,
+    "complex64": (8387.3 * 2.0 + 16388.3) * 1024,
 }
 
 
