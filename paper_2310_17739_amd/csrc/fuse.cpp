@@ -27,9 +27,13 @@
 namespace qs {
 
 double max_abs(const cd *m, size_t n) {
-    double r = 0;
-    for (size_t i = 0; i < n; i++) r = std::max(r, std::abs(m[i]));
-    return r;
+    // the largest squared modulus, one square root at the end
+    double r2 = 0;
+    for (size_t i = 0; i < n; i++) {
+        const double a = m[i].real(), b = m[i].imag();
+        r2 = std::max(r2, a * a + b * b);
+    }
+    return std::sqrt(r2);
 }
 
 // Bit m of *present is set when some row r has M[r][r ^ m] above tol.
@@ -287,7 +291,9 @@ void fuse_f2(int n, Lowered *L, const FuseConfig &cfg, bool ordered,
 }
 
 // Level 5: cost-driven merge into operators of up to max_width qubits.
-void fuse_width(int n, Lowered *L, const FuseConfig &cfg) {
+// Returns the cost of the resulting list: the sum, in list order, of each
+// operator's terms (op_terms; 2^k when not sparse) plus lds_cost.
+double fuse_width(int n, Lowered *L, const FuseConfig &cfg) {
     const std::vector<int> *ep = &L->op_epoch;
     const double tol = 1e-14;
     std::vector<Op> out;
@@ -335,13 +341,9 @@ void fuse_width(int n, Lowered *L, const FuseConfig &cfg) {
     }
     L->ops.swap(out);
     L->op_epoch.swap(out_ep);
-}
-
-// Cost of an operator list under the level-5 model.
-double list_cost(const std::vector<Op> &ops, const FuseConfig &cfg) {
-    const double tol = 1e-14;
+    // out_terms holds each operator's terms as op_terms counts them
     double c = 0;
-    for (const Op &o : ops) c += (cfg.sparse ? op_terms(o, tol) : (1 << o.k)) + cfg.lds_cost;
+    for (int t : out_terms) c += t + cfg.lds_cost;
     return c;
 }
 
@@ -491,8 +493,11 @@ struct RunTable {
     uint8_t k[kMaxRun];
 };
 
-void fuse_runs(Lowered *L, const FuseConfig &cfg) {
+// Reads `in` only; returns the cost of the chosen list, summed as
+// fuse_width sums its own.
+double fuse_runs(const Lowered &in, const FuseConfig &cfg, Lowered *out) {
     const double tol = 1e-14;
+    const Lowered *L = &in;
     const size_t N = L->ops.size();
     std::vector<double> best(N + 1, 1e300);
     std::vector<int> from(N + 1, -1);
@@ -589,8 +594,9 @@ void fuse_runs(Lowered *L, const FuseConfig &cfg) {
     std::reverse(runs.begin(), runs.end());
     // each run's dense product (independent of the others: several threads,
     // each on a contiguous range of runs)
-    std::vector<Op> out(runs.size());
+    std::vector<Op> fused(runs.size());
     std::vector<int> out_ep(runs.size());
+    std::vector<int> terms(runs.size());
     const size_t nr = runs.size();
     const int use = int(std::min<size_t>(size_t(nth), (nr + 1023) / 1024));
     std::vector<char> failed(size_t(std::max(use, 1)), 0);
@@ -606,7 +612,8 @@ void fuse_runs(Lowered *L, const FuseConfig &cfg) {
                     mul_small(&cur, L->ops[size_t(i)], true);
                 }
                 out_ep[j] = L->op_epoch[size_t(r.first)];
-                out[j] = std::move(cur);
+                terms[j] = cfg.sparse ? op_terms(cur, tol) : (1 << cur.k);
+                fused[j] = std::move(cur);
             }
         } catch (const std::bad_alloc &) {
             failed[size_t(w)] = 1;
@@ -620,17 +627,15 @@ void fuse_runs(Lowered *L, const FuseConfig &cfg) {
         for (char f : failed)
             if (f) throw std::bad_alloc();
     }
-    L->ops.swap(out);
-    L->op_epoch.swap(out_ep);
+    out->ops.swap(fused);
+    out->op_epoch.swap(out_ep);
+    double c = 0;
+    for (int t : terms) c += t + cfg.lds_cost;
+    return c;
 }
 
-}  // namespace
-
-void fuse(int n, Lowered *L, const FuseConfig &cfg, int64_t counts[6]) {
-    for (int l = 0; l < 6; l++) counts[l] = -1;
-    counts[0] = int64_t(L->ops.size());
-    Lowered runs;
-    if (cfg.level >= 5) runs = *L;
+// The paper's passes, levels 1-4 (level 5 starts from level 4's list).
+void fuse_paper(int n, Lowered *L, const FuseConfig &cfg, int64_t counts[6]) {
     if (cfg.level >= 1) { fuse_f1(n, L, cfg); counts[1] = int64_t(L->ops.size()); }
     if (cfg.level >= 2) { fuse_f3(n, L, cfg); counts[2] = int64_t(L->ops.size()); }
     if (cfg.level == 3) {
@@ -648,26 +653,46 @@ void fuse(int n, Lowered *L, const FuseConfig &cfg, int64_t counts[6]) {
         compact(L);
         counts[3] = counts[4] = int64_t(L->ops.size());
     }
-    if (cfg.level >= 5) {
-        // two candidates, the cheaper under the cost model wins: the greedy
+}
+
+}  // namespace
+
+void fuse(int n, Lowered *L, const FuseConfig &cfg, int64_t counts[6]) {
+    for (int l = 0; l < 6; l++) counts[l] = -1;
+    counts[0] = int64_t(L->ops.size());
+    if (cfg.level < 5) {
+        fuse_paper(n, L, cfg, counts);
+        return;
+    }
+    {
+        // Two candidates, the cheaper under the cost model wins: the greedy
         // merge of the F1-F4 operators (any that commute into place) and the
         // best partition of the unfused gate list into runs of consecutive
-        // gates
-        // (independent: computed side by side)
+        // gates.  They are independent: the partition starts at once on its
+        // own thread, reading *L, while this thread runs F1-F4 and the greedy
+        // merge on a copy.
+        Lowered runs, mine;
+        double runs_cost = 0, width_cost = 0;
         bool runs_ok = true;
-        std::thread th([&runs, &cfg, &runs_ok] {
+        std::thread th([L, &runs, &cfg, &runs_ok, &runs_cost] {
             try {
-                fuse_runs(&runs, cfg);
+                runs_cost = fuse_runs(*L, cfg, &runs);
             } catch (const std::bad_alloc &) {
                 runs_ok = false;
             }
         });
-        fuse_width(n, L, cfg);
-        th.join();
-        if (runs_ok && list_cost(runs.ops, cfg) < list_cost(L->ops, cfg)) {
-            L->ops.swap(runs.ops);
-            L->op_epoch.swap(runs.op_epoch);
+        try {
+            mine = *L;
+            fuse_paper(n, &mine, cfg, counts);
+            width_cost = fuse_width(n, &mine, cfg);
+        } catch (...) {
+            th.join();
+            throw;
         }
+        th.join();
+        Lowered &win = (runs_ok && runs_cost < width_cost) ? runs : mine;
+        L->ops.swap(win.ops);
+        L->op_epoch.swap(win.op_epoch);
         counts[5] = int64_t(L->ops.size());
     }
 }
