@@ -423,26 +423,37 @@ void xop_left_mul(const Op &o, uint32_t gp, const XOp &cur, XOp *out) {
     for (int r = 0; r < D; r++) gi[r] = gather_bits(r, sel, o.k);
     out->k = cur.k;
     std::copy(cur.q, cur.q + kMaxK, out->q);
-    out->present = 0;
+    uint32_t present = 0;
     for (uint32_t pg = gp; pg; pg &= pg - 1) {
         const int gm = __builtin_ctz(pg);
         const int gmm = scatter_bits(gm, sel, o.k);
-        cd gd[1 << kMaxK];
-        for (int r = 0; r < D; r++) gd[r] = o.m[size_t(gi[r]) * Do + (gi[r] ^ gm)];
+        double gre[1 << kMaxK], gim[1 << kMaxK];
+        for (int r = 0; r < D; r++) {
+            const cd v = o.m[size_t(gi[r]) * Do + (gi[r] ^ gm)];
+            gre[r] = v.real();
+            gim[r] = v.imag();
+        }
         for (uint32_t pm = cur.present; pm; pm &= pm - 1) {
             const int m = __builtin_ctz(pm);
             const int t = gmm ^ m;
-            if (!(out->present & (1u << t))) {
-                out->present |= 1u << t;
-                for (int r = 0; r < D; r++) out->d[t][r] = cd(0);
-            }
-            for (int r = 0; r < D; r++) {
-                const cd a = gd[r], b = cur.d[m][r ^ gmm];
-                out->d[t][r] += cd(a.real() * b.real() - a.imag() * b.imag(),
-                                   a.real() * b.imag() + a.imag() * b.real());
+            const cd *src = cur.d[m];
+            cd *dst = out->d[t];
+            if (!(present & (1u << t))) {
+                // first contribution to row t
+                present |= 1u << t;
+                for (int r = 0; r < D; r++) {
+                    const cd b = src[r ^ gmm];
+                    dst[r] = cd(gre[r] * b.real() - gim[r] * b.imag(), gre[r] * b.imag() + gim[r] * b.real());
+                }
+            } else {
+                for (int r = 0; r < D; r++) {
+                    const cd b = src[r ^ gmm];
+                    dst[r] += cd(gre[r] * b.real() - gim[r] * b.imag(), gre[r] * b.imag() + gim[r] * b.real());
+                }
             }
         }
     }
+    out->present = present;
 }
 
 // Terms above rel_tol times the largest entry (as op_terms counts them).
