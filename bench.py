@@ -188,6 +188,7 @@ def run_trajectories(qsim, W, ntraj=1024, rounds=500):
     res = b.qsim_batch_results(0)
     dt = time.perf_counter() - t0
     info = b.qsim_batch_info()
+    terms = b.qsim_batch_group_stats(0)["terms"]
     b.close()
     p = res["probs"]
     # The 128 KiB state stays in one workgroup's LDS for the whole program, so
@@ -196,12 +197,18 @@ def run_trajectories(qsim, W, ntraj=1024, rounds=500):
     # it (counted as one more read and write; a reset that follows a
     # measurement of its qubit runs inside that measurement's record).
     lds_bytes = ntraj * (info["fused_ops"] + info["records"]) * 2 * 8 * (1 << 14)
+    flops = ntraj * terms * 8 * (1 << 14)
     return {"workload": f"{ntraj} trajectories x {rounds} rounds, 14 qubits, complex64",
             "seconds": dt, "trajectory_rounds_per_s": ntraj * rounds / dt,
             "input_gates_per_s": ntraj * len(g) / dt, "passes": info["passes"],
             "fused_ops_per_trajectory": info["fused_ops"], "records_per_trajectory": info["records"],
             "lds": {"bytes": lds_bytes, "achieved_GBps": lds_bytes / dt / 1e9, "peak_GBps": LDS_PEAK_GBS,
                     "frac": lds_bytes / dt / 1e9 / LDS_PEAK_GBS},
+            # every XOR-shift term is one complex multiply-add (8 flops) per
+            # amplitude; vector FP32 without packed instructions peaks at the
+            # FP64 rate, 78.6 TFLOP/s
+            "alu": {"flops": flops, "achieved_TFLOPs": flops / dt / 1e12, "peak_TFLOPs": 78.6,
+                    "frac": flops / dt / 1e12 / 78.6},
             "failed": int((res["status"] != 0).sum()),
             "mean_p_outcome": float(p.mean()), "norm_max_dev": float(np.abs(res["norms"] - 1).max())}
 
