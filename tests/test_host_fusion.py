@@ -248,3 +248,19 @@ def test_allocation_failure_reports_nomem_once():
     again = qsim.qsim_debug_plan(8, g)
     assert again["passes"] == ok["passes"] and again["fused_ops"] == ok["fused_ops"]
     qsim.qsim_debug_fail_alloc(-1)
+
+
+def test_level5_fusion_is_deterministic():
+    """Level 5 computes its two candidates on concurrent threads (the run
+    partition on its own worker pool, F1-F4 and the greedy merge beside it)
+    and keeps the cheaper: the operators chosen, and every matrix entry,
+    must not depend on thread timing."""
+    g, _, _ = W.pauli_exponential_circuit(12, 1500, seed=5)
+    runs = [qsim.qsim_debug_fuse(12, g, level=5, max_width=4) for _ in range(3)]
+    ops0, counts0 = runs[0]
+    for ops, counts in runs[1:]:
+        assert list(counts) == list(counts0)
+        assert len(ops) == len(ops0)
+        for (qa, ma), (qb, mb) in zip(ops, ops0):
+            assert tuple(qa) == tuple(qb)
+            assert np.array_equal(ma, mb)
