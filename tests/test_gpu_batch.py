@@ -164,6 +164,39 @@ def test_reset_folding(Q, dtype, n, tile, monkeypatch):
         assert oracle.infidelity(states[t], states2[t]) < tol
 
 
+@pytest.mark.parametrize("dtype,n,tile", [("complex128", 6, None), ("complex64", 6, None),
+                                          ("complex128", 15, 10), ("complex64", 15, 10)])
+def test_joined_measure_reset_zero_probability(Q, dtype, n, tile):
+    """X then Ry(theta_b) on qubit 0, a measurement forced to 0, a reset of
+    qubit 0 (joined to the measurement), a CNOT.  theta = 0 leaves
+    P(0) = 0: that state fails with QSIM_E_ZERO_PROB and keeps its value
+    from before the record; the others collapse to |0> on qubit 0 and go
+    on, as the oracle does with the records as written."""
+    recs = [(W.KIND_H, (1,), ()), (W.KIND_X, (0,), ()), (W.KIND_RY, (0,), (0.0,), 0),
+            (W.KIND_MEASURE, (0,), (), 0), (W.KIND_RESET, (0,), ()), (W.KIND_CX, (1, n - 1), ())]
+    g = W.gates(recs)
+    thetas = np.array([[0.7], [0.0], [2.0], [1.3]])
+    forced = np.zeros((4, 1), dtype=np.int32)
+    kw = {} if tile is None else {"tile_qubits": tile}
+    say("joined measure-reset, zero probability", dtype, n, tile)
+    u = W.uniforms((4, 1), seed=3)   # measurements take draws even where every outcome is forced
+    b = Q.Batch([{"n": n, "n_states": 4, "gates": g, "params": thetas, "uniforms": u, "forced": forced,
+                  "n_slots": 1}], dtype=dtype, **kw)
+    b.qsim_batch_run()
+    res = b.qsim_batch_results(0)
+    assert b.qsim_batch_info()["records"] == 1
+    assert list(res["status"]) == [0, Q.E_ZERO_PROB, 0, 0]
+    tol = 1e-12 if dtype == "complex128" else 1e-5
+    for s_ in (0, 2, 3):
+        psi, oo, pr = oracle.run(n, g, params=thetas[s_], uniforms=u[s_], forced=forced[s_], n_slots=1)
+        assert res["outcomes"][s_][0] == oo[0] == 0
+        assert abs(res["probs"][s_][0] - pr[0]) < (1e-12 if dtype == "complex128" else 2e-5)
+        assert oracle.infidelity(psi, b.qsim_batch_get_state(0, s_)) < tol
+    before, _, _ = oracle.run(n, g[:3], params=thetas[1])
+    assert oracle.infidelity(before, b.qsim_batch_get_state(0, 1)) < tol
+    b.close()
+
+
 @pytest.mark.parametrize("n", [6, 15])
 def test_assertion_failure_marks_only_that_state(Q, n):
     """X then Ry(theta_b) on the ancilla, then ASSERT0: theta = 0 leaves the
