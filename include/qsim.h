@@ -287,7 +287,8 @@ typedef struct qsim_batch_group {
     const double *params;    /* n_states x n_params angles read by records with
                                 slot >= 0 (RX, RY, RZ, RXX, RZZ), or NULL */
     int32_t n_params;
-    const double *uniforms;  /* n_states x n_slots draws in [0,1), or NULL */
+    const double *uniforms;  /* n_states x n_slots draws in [0,1), or NULL (then the
+                                program may hold no MEASURE record: QSIM_E_ARG) */
     const int32_t *forced;   /* n_states x n_slots outcomes to force (-1: draw), or NULL */
     int32_t n_slots;         /* measurement slots per state */
     const qsim_pauli *terms; /* observable evaluated at the end, or NULL */
@@ -325,7 +326,8 @@ typedef struct qsim_batch_info {
 
 /* Compile every group once (lowering, fusion, plan; angle-dependent
  * operators keep their cos/sin basis blocks) and allocate device memory.
- * Errors as qsim_compile, plus QSIM_E_CAPACITY (n_states > 65535). */
+ * Errors as qsim_compile, plus QSIM_E_CAPACITY (n_states > 65535) and
+ * QSIM_E_ARG for a MEASURE record in a group without uniforms. */
 int qsim_batch_create(const qsim_batch_group *groups, int n_groups, const qsim_batch_opts *opt,
                       qsim_batch_h *out);
 /* Run every group from |0...0> (asynchronous on hip_stream): bind angles,
