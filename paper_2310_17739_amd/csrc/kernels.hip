@@ -1171,14 +1171,10 @@ __global__ void __launch_bounds__(NT) k_init_zero(Cx<T> *__restrict__ state, uin
 template <typename T>
 __global__ void __launch_bounds__(NT) k_collapse(Cx<T> *__restrict__ state, uint64_t len, int q,
                                                  int outcome, T scale) {
-    // the other outcome's amplitudes are overwritten without being read
     for (uint64_t i = uint64_t(blockIdx.x) * NT + threadIdx.x; i < len; i += uint64_t(gridDim.x) * NT) {
-        Cx<T> a{T(0), T(0)};
-        if (int((i >> q) & 1) == outcome) {
-            a = state[i];
-            a.re *= scale;
-            a.im *= scale;
-        }
+        Cx<T> a = state[i];
+        if (int((i >> q) & 1) == outcome) { a.re *= scale; a.im *= scale; }
+        else a = Cx<T>{T(0), T(0)};
         state[i] = a;
     }
 }
@@ -1375,18 +1371,16 @@ __global__ void __launch_bounds__(NT) k_decide(Cx<T> *__restrict__ state, uint64
     const T scale = T(1.0 / sqrt(kept));
     Cx<T> *st = state + size_t(b) * sstride;
     const uint64_t half = uint64_t(1) << (n - 1), bq = uint64_t(1) << q;
-    // One amplitude of each pair survives (the outcome's, or |1>'s for a
-    // reset): only that one is read.  It lands at x0 unless a measurement
-    // without reset kept outcome 1.
-    const bool from1 = swap || o == 1;
-    const bool to0 = swap || o == 0 || to_zero;
-    const Cx<T> zero{T(0), T(0)};
     for (uint64_t g = uint64_t(blockIdx.x) * NT + threadIdx.x; g < half; g += uint64_t(gridDim.x) * NT) {
         const uint64_t x0 = ((g >> q) << (q + 1)) | (g & (bq - 1)), x1 = x0 | bq;
-        const Cx<T> a = st[from1 ? x1 : x0];
-        const Cx<T> v = swap ? a : Cx<T>{a.re * scale, a.im * scale};
-        st[x0] = to0 ? v : zero;
-        st[x1] = to0 ? zero : v;
+        const Cx<T> a0 = st[x0], a1 = st[x1];
+        Cx<T> n0, n1 = Cx<T>{T(0), T(0)};
+        if (swap) n0 = a1;
+        else if (o == 0) n0 = Cx<T>{a0.re * scale, a0.im * scale};
+        else if (to_zero) n0 = Cx<T>{a1.re * scale, a1.im * scale};
+        else { n0 = Cx<T>{T(0), T(0)}; n1 = Cx<T>{a1.re * scale, a1.im * scale}; }
+        st[x0] = n0;
+        st[x1] = n1;
     }
 }
 
