@@ -12,6 +12,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <new>
+#include <thread>
 
 #include <rocprofiler-sdk-roctx/roctx.h>
 
@@ -270,15 +272,86 @@ void to_sorted(const int *qs, int k, const cd *src, int nblocks, Op *op) {
 
 }  // namespace
 
+namespace {
+
+// One gate record (not a barrier or a measurement record) -> its operator.
+// Returns QSIM_OK or the record's error.
+int lower_gate(int n, const qsim_gate &gi, const GateInputs &in, bool keep_params, Op *out,
+               std::vector<cd> &m, std::vector<cd> &m2) {
+    int k = gi.nq;
+    if (k < 1 || k > kMaxK) return QSIM_E_ARG;
+    if (gi.kind != QSIM_G_MAT && kind_arity(gi.kind) != k)
+        return kind_arity(gi.kind) ? QSIM_E_ARG : QSIM_E_UNSUPPORTED;
+    for (int j = 0; j < k; j++) {
+        if (gi.q[j] < 0 || gi.q[j] >= n) return QSIM_E_QUBIT;
+        for (int l = 0; l < j; l++)
+            if (gi.q[l] == gi.q[j]) return QSIM_E_QUBIT;
+    }
+    double th[3] = {gi.theta[0], gi.theta[1], gi.theta[2]};
+    bool symbolic = false;
+    if (gi.slot >= 0) {
+        if (keep_params) {
+            if (!is_half_angle_linear(gi.kind)) return QSIM_E_UNSUPPORTED;
+            if (size_t(gi.slot) >= in.n_params) return QSIM_E_ARG;
+            symbolic = true;
+        } else {
+            if (!in.params || size_t(gi.slot) >= in.n_params) return QSIM_E_ARG;
+            th[0] = in.params[gi.slot];
+        }
+    }
+    for (double v : th)
+        if (!std::isfinite(v)) return QSIM_E_ARG;
+    Op op;
+    op.src_kind = gi.kind;
+    op.orient = (k == 2 && gi.q[0] > gi.q[1]) ? 1 : 0;
+    int d = 1 << k;
+    if (gi.kind == QSIM_G_MAT) {
+        if (!in.mats || size_t(gi.mat_off) + size_t(d) * d > in.n_mats) return QSIM_E_ARG;
+        const double *mats = in.mats;
+        m.resize(size_t(d) * d);
+        const double *src = mats + 2 * size_t(gi.mat_off);
+        for (int e = 0; e < d * d; e++) {
+            m[e] = cd(src[2 * e], src[2 * e + 1]);
+            if (!std::isfinite(m[e].real()) || !std::isfinite(m[e].imag())) return QSIM_E_ARG;
+        }
+        to_sorted(gi.q, k, m.data(), 1, &op);
+    } else if (symbolic) {
+        // basis blocks: theta = 0 gives the cos(theta/2) block, theta = pi the sin block
+        double t0[3] = {0.0, th[1], th[2]}, t1[3] = {M_PI, th[1], th[2]};
+        int rc = gate_matrix(gi, t0, &m);
+        if (rc) return rc;
+        rc = gate_matrix(gi, t1, &m2);
+        if (rc) return rc;
+        m.insert(m.end(), m2.begin(), m2.end());
+        to_sorted(gi.q, k, m.data(), 2, &op);
+        op.np = 1;
+        op.slot[0] = gi.slot;
+    } else {
+        int rc = gate_matrix(gi, th, &m);
+        if (rc) return rc;
+        to_sorted(gi.q, k, m.data(), 1, &op);
+    }
+    *out = std::move(op);
+    return QSIM_OK;
+}
+
+}  // namespace
+
 int lower(int n, const qsim_gate *g, size_t ng, const GateInputs &in, bool keep_params,
           bool allow_meas, Lowered *out) {
     out->ops.clear();
     out->op_epoch.clear();
     out->meas.clear();
     out->input_gates = 0;
-    out->ops.reserve(ng);
-    out->op_epoch.reserve(ng);
+    // First, in record order: epochs, measurement records and the gate
+    // record of every operator.  Then the operators themselves, which are
+    // independent, on several threads.  The first failing record in
+    // program order decides the error.
+    std::vector<size_t> op_gate;
+    op_gate.reserve(ng);
     int epoch = 0;
+    int first_rc = QSIM_OK;
+    size_t first_at = ng;
     // Records out->meas[run_begin ..] follow each other with no operator or
     // barrier between them.  Non-unitary steps on different qubits commute,
     // and after a measurement, an assertion or a reset the qubit is definite,
@@ -290,8 +363,7 @@ int lower(int n, const qsim_gate *g, size_t ng, const GateInputs &in, bool keep_
     const char *fv = std::getenv("QSIM_FOLD_RESETS");
     const bool fold_resets = !(fv && *fv && std::atoi(fv) == 0);
     size_t run_begin = 0;
-    std::vector<cd> m, m2;
-    for (size_t i = 0; i < ng; i++) {
+    for (size_t i = 0; i < ng && first_at == ng; i++) {
         const qsim_gate &gi = g[i];
         if (gi.kind == QSIM_G_BARRIER) {
             epoch++;
@@ -299,10 +371,16 @@ int lower(int n, const qsim_gate *g, size_t ng, const GateInputs &in, bool keep_
             continue;
         }
         if (gi.kind == QSIM_G_MEASURE || gi.kind == QSIM_G_RESET || gi.kind == QSIM_G_ASSERT0) {
-            if (!allow_meas) return QSIM_E_UNSUPPORTED;
-            if (gi.nq != 1) return QSIM_E_ARG;
-            if (gi.q[0] < 0 || gi.q[0] >= n) return QSIM_E_QUBIT;
-            if (gi.kind != QSIM_G_RESET && gi.slot < 0) return QSIM_E_ARG;
+            int rc = QSIM_OK;
+            if (!allow_meas) rc = QSIM_E_UNSUPPORTED;
+            else if (gi.nq != 1) rc = QSIM_E_ARG;
+            else if (gi.q[0] < 0 || gi.q[0] >= n) rc = QSIM_E_QUBIT;
+            else if (gi.kind != QSIM_G_RESET && gi.slot < 0) rc = QSIM_E_ARG;
+            if (rc) {
+                first_rc = rc;
+                first_at = i;
+                break;
+            }
             if (gi.kind == QSIM_G_RESET && fold_resets) {
                 bool folded = false;
                 for (size_t j = out->meas.size(); j > run_begin; j--) {
@@ -324,64 +402,51 @@ int lower(int n, const qsim_gate *g, size_t ng, const GateInputs &in, bool keep_
             epoch++;
             continue;
         }
-        int k = gi.nq;
-        if (k < 1 || k > kMaxK) return QSIM_E_ARG;
-        if (gi.kind != QSIM_G_MAT && kind_arity(gi.kind) != k)
-            return kind_arity(gi.kind) ? QSIM_E_ARG : QSIM_E_UNSUPPORTED;
-        for (int j = 0; j < k; j++) {
-            if (gi.q[j] < 0 || gi.q[j] >= n) return QSIM_E_QUBIT;
-            for (int l = 0; l < j; l++)
-                if (gi.q[l] == gi.q[j]) return QSIM_E_QUBIT;
-        }
-        double th[3] = {gi.theta[0], gi.theta[1], gi.theta[2]};
-        bool symbolic = false;
-        if (gi.slot >= 0) {
-            if (keep_params) {
-                if (!is_half_angle_linear(gi.kind)) return QSIM_E_UNSUPPORTED;
-                if (size_t(gi.slot) >= in.n_params) return QSIM_E_ARG;
-                symbolic = true;
-            } else {
-                if (!in.params || size_t(gi.slot) >= in.n_params) return QSIM_E_ARG;
-                th[0] = in.params[gi.slot];
-            }
-        }
-        for (double v : th)
-            if (!std::isfinite(v)) return QSIM_E_ARG;
-        Op op;
-        op.src_kind = gi.kind;
-        op.orient = (k == 2 && gi.q[0] > gi.q[1]) ? 1 : 0;
-        int d = 1 << k;
-        if (gi.kind == QSIM_G_MAT) {
-            if (!in.mats || size_t(gi.mat_off) + size_t(d) * d > in.n_mats) return QSIM_E_ARG;
-            const double *mats = in.mats;
-            m.resize(size_t(d) * d);
-            const double *src = mats + 2 * size_t(gi.mat_off);
-            for (int e = 0; e < d * d; e++) {
-                m[e] = cd(src[2 * e], src[2 * e + 1]);
-                if (!std::isfinite(m[e].real()) || !std::isfinite(m[e].imag())) return QSIM_E_ARG;
-            }
-            to_sorted(gi.q, k, m.data(), 1, &op);
-        } else if (symbolic) {
-            // basis blocks: theta = 0 gives the cos(theta/2) block, theta = pi the sin block
-            double t0[3] = {0.0, th[1], th[2]}, t1[3] = {M_PI, th[1], th[2]};
-            int rc = gate_matrix(gi, t0, &m);
-            if (rc) return rc;
-            rc = gate_matrix(gi, t1, &m2);
-            if (rc) return rc;
-            m.insert(m.end(), m2.begin(), m2.end());
-            to_sorted(gi.q, k, m.data(), 2, &op);
-            op.np = 1;
-            op.slot[0] = gi.slot;
-        } else {
-            int rc = gate_matrix(gi, th, &m);
-            if (rc) return rc;
-            to_sorted(gi.q, k, m.data(), 1, &op);
-        }
-        out->ops.push_back(std::move(op));
+        op_gate.push_back(i);
         out->op_epoch.push_back(epoch);
-        out->input_gates++;
         run_begin = out->meas.size();
     }
+    // the operators, in contiguous ranges; each range keeps its first error
+    const size_t nops = op_gate.size();
+    out->ops.resize(nops);
+    const size_t kPerThread = 16384;
+    const int nth = int(std::min<size_t>(size_t(std::max(1, std::min(16, int(std::thread::hardware_concurrency())))),
+                                         (nops + kPerThread - 1) / kPerThread));
+    std::vector<int> rcs(size_t(std::max(nth, 1)), QSIM_OK);
+    std::vector<size_t> at(size_t(std::max(nth, 1)), ng);
+    std::vector<char> oom(size_t(std::max(nth, 1)), 0);
+    auto work = [&](int w) {
+        try {
+            std::vector<cd> m, m2;
+            for (size_t j = nops * size_t(w) / size_t(nth); j < nops * size_t(w + 1) / size_t(nth); j++) {
+                const int rc = lower_gate(n, g[op_gate[j]], in, keep_params, &out->ops[j], m, m2);
+                if (rc) {
+                    rcs[size_t(w)] = rc;
+                    at[size_t(w)] = op_gate[j];
+                    return;
+                }
+            }
+        } catch (const std::bad_alloc &) {
+            oom[size_t(w)] = 1;
+        }
+    };
+    if (nth > 1) {
+        std::vector<std::thread> th;
+        for (int w = 1; w < nth; w++) th.emplace_back(work, w);
+        work(0);
+        for (auto &x : th) x.join();
+    } else if (nth == 1) {
+        work(0);
+    }
+    for (char f : oom)
+        if (f) throw std::bad_alloc();
+    for (size_t w = 0; w < rcs.size(); w++)
+        if (rcs[w] && at[w] < first_at) {
+            first_at = at[w];
+            first_rc = rcs[w];
+        }
+    if (first_rc) return first_rc;
+    out->input_gates = int64_t(nops);
     out->n_epochs = epoch + 1;
     return QSIM_OK;
 }

@@ -264,3 +264,22 @@ def test_level5_fusion_is_deterministic():
         for (qa, ma), (qb, mb) in zip(ops, ops0):
             assert tuple(qa) == tuple(qb)
             assert np.array_equal(ma, mb)
+
+
+@pytest.mark.parametrize("first", ["qubit", "arg", "record"])
+def test_first_bad_record_decides_the_error(first):
+    """Lowering builds the operators of a long circuit on several threads;
+    the error reported is still that of the first bad record in program
+    order (a qubit out of range, a non-finite angle, a measurement record
+    where none is allowed)."""
+    n = 8
+    g = W.random_circuit(n, 60000, seed=3)
+    bad_q = W.gates([(W.KIND_H, (n,), ())])[0]
+    bad_a = W.gates([(W.KIND_RX, (1,), (float("nan"),))])[0]
+    rec = W.gates([(W.KIND_MEASURE, (0,), (), 0)])[0]
+    order = {"qubit": (bad_q, bad_a, rec), "arg": (bad_a, rec, bad_q), "record": (rec, bad_q, bad_a)}[first]
+    for pos, r in zip((7000, 31000, 52000), order):
+        g[pos] = r
+    with pytest.raises(qsim.QsimError) as e:
+        qsim.qsim_debug_plan(n, g, "complex128")
+    assert e.value.code == {"qubit": qsim.E_QUBIT, "arg": qsim.E_ARG, "record": qsim.E_UNSUPPORTED}[first]
