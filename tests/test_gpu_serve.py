@@ -66,6 +66,10 @@ def test_served_results_match_oracle(Q, dtype):
 
 
 def test_alone_equals_in_mix(Q):
+    """The probe's state, <H> and norm are bit-identical run alone and in a
+    mix.  The mix starts with a long anchor request (19 qubits, 20,000
+    exponentials); the probe and the others are submitted once the anchor
+    is admitted, so the probe runs while the anchor is resident."""
     reqs = requests(2, 16, 10, 19)
     probe = reqs[7]
     alone = Q.Server(dtype="complex64", slots=1, compile_threads=1, pool_bytes=64 << 20)
@@ -73,15 +77,24 @@ def test_alone_equals_in_mix(Q):
     a = collect(alone, 1)[a_id]
     alone.close()
     mix = Q.Server(dtype="complex64", slots=8, compile_threads=4, pool_bytes=64 << 20)
-    ids = [mix.qsim_server_submit(w, g, terms=H, want_state=(i == 7)) for i, (w, g, H) in enumerate(reqs)]
-    got = collect(mix, len(ids))
+    anchor = W.pauli_exponential_circuit(19, 20000, seed=77)[0]
+    anchor_id = mix.qsim_server_submit(19, anchor)
+    t0 = time.time()
+    while mix.qsim_server_stats()["in_flight"] < 1:
+        assert time.time() - t0 < 60, "the anchor was not admitted"
+        time.sleep(0.0005)
+    order = [7] + [i for i in range(len(reqs)) if i != 7]
+    ids = {i: mix.qsim_server_submit(reqs[i][0], reqs[i][1], terms=reqs[i][2], want_state=(i == 7))
+           for i in order}
+    got = collect(mix, len(ids) + 1)
     m = got[ids[7]]
     assert np.array_equal(m["state"], a["state"])
     assert m["expval"] == a["expval"] and m["norm"] == a["norm"]
-    # the probe shared the device: its admit..done interval overlaps another
-    # request's, and several requests were resident at once
-    overlaps = [i for i in ids if i != ids[7] and got[i]["t_admit"] < m["t_done"] and m["t_admit"] < got[i]["t_done"]]
-    assert overlaps, "the probe ran alone in the mix"
+    # the probe shared the device: its admit..done interval lies inside the
+    # anchor's, and several requests were resident at once
+    an = got[anchor_id]
+    assert an["status"] == 0
+    assert an["t_admit"] < m["t_admit"] and m["t_done"] < an["t_done"], "the probe ran alone in the mix"
     assert mix.qsim_server_stats()["peak_in_flight"] > 1
     mix.close()
 
