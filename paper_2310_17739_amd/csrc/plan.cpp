@@ -49,14 +49,16 @@ OpClass op_class(const Op &o) {
     c.q = o.mask();
     if (o.np > 0 || o.m.empty()) return c;
     const int d = o.dim();
-    double mx = 0.0;
-    for (const cd &v : o.m) mx = std::max(mx, std::abs(v));
-    const double tol = 1e-13 * mx;
+    // moduli compared through their squares: |v| > tol  <=>  |v|^2 > tol^2
+    auto n2 = [](cd v) { return v.real() * v.real() + v.imag() * v.imag(); };
+    double mx2 = 0.0;
+    for (const cd &v : o.m) mx2 = std::max(mx2, n2(v));
+    const double tol2 = 1e-26 * mx2;   // (1e-13 times the largest modulus)^2
     auto at = [&](int r, int col) { return o.m[size_t(r) * d + size_t(col)]; };
     uint32_t present = 0;
     for (int s = 0; s < d; s++)
         for (int r = 0; r < d; r++)
-            if (std::abs(at(r, r ^ s)) > tol) { present |= 1u << s; break; }
+            if (n2(at(r, r ^ s)) > tol2) { present |= 1u << s; break; }
     if (present == 1u) {
         c.kind = 1;
         return c;
@@ -67,18 +69,18 @@ OpClass op_class(const Op &o) {
     const int X = __builtin_ctz(others);
     if (present & 1u)
         for (int r = 1; r < d; r++)
-            if (std::abs(at(r, r) - at(0, 0)) > tol) return c;
+            if (n2(at(r, r) - at(0, 0)) > tol2) return c;
     // the shift's entries: a common value times the signs (-1)^popcount(r & z)
     const cd d0 = at(0, X);
     int zl = 0;
     for (int j = 0; j < o.k; j++) {
         const cd v = at(1 << j, (1 << j) ^ X);
-        if (std::abs(v + d0) <= tol) zl |= 1 << j;
-        else if (std::abs(v - d0) > tol) return c;
+        if (n2(v + d0) <= tol2) zl |= 1 << j;
+        else if (n2(v - d0) > tol2) return c;
     }
     for (int r = 0; r < d; r++) {
         const double sg = (__builtin_popcount(r & zl) & 1) ? -1.0 : 1.0;
-        if (std::abs(at(r, r ^ X) - sg * d0) > tol) return c;
+        if (n2(at(r, r ^ X) - sg * d0) > tol2) return c;
     }
     c.kind = 2;
     for (int j = 0; j < o.k; j++) {
